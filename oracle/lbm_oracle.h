@@ -1,0 +1,92 @@
+/*
+ * FP64 CPU oracle of the thermal multiphase lattice Boltzmann method of
+ * Kupershtokh, Medvedev and Gribanov, "Thermal lattice Boltzmann method for
+ * multiphase flows" (arXiv:1705.10045).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this library.  The product (the HIP
+ * library under paper_1705_10045_amd/) shares no code, header, table or
+ * constant with it.
+ *
+ * Layout of every field argument: row-major over nodes, idx = x + nx*(y + ny*z);
+ * vector fields are three consecutive planes [vx(n) | vy(n) | vz(n)].
+ * Populations inside the oracle are node-major (AoS): f[idx*Q + k].
+ */
+#ifndef LBM_ORACLE_H
+#define LBM_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Physical terms that can be switched on and off (the ablations of sections 4-6). */
+#define ORC_WORK        1u   /* pressure work -p div u*                              */
+#define ORC_CONDUCTION  2u   /* heat conduction div(lambda grad T)                   */
+#define ORC_LATENT      4u   /* latent heat inside the transition layer (section 5)  */
+#define ORC_PSEUDOFORCE 8u   /* EDM "pseudoforces" on the energy populations         */
+#define ORC_BAROTROPIC 16u   /* EOS at the fixed temperature T0_baro (section 4)     */
+
+#define ORC_OK         0
+#define ORC_EINVAL    -1
+#define ORC_EUNSTABLE -3
+
+typedef struct {
+    int Q;                 /* 9 (D2Q9, nz must be 1) or 19 (D3Q19)            */
+    int nx, ny, nz;        /* periodic box                                    */
+    double tau, tau_E;     /* BGK relaxation times of N_k and g_k             */
+    double A;              /* force mixing parameter (section 3)              */
+    double rho_c, T_c, p_c;/* critical point of the van der Waals fluid       */
+    double c_v, chi, rhoQ; /* specific heat, thermal diffusivity, rho_liq*Q   */
+    double T0_baro;        /* EOS temperature when ORC_BAROTROPIC is set      */
+    unsigned flags;
+} orc_params;
+
+/* Lattice tables: c[Q*3], w[Q], G[Q] (G[0] = 0), alpha.  Returns D or ORC_EINVAL. */
+int orc_lattice(int Q, int* c, double* w, double* G, double* alpha);
+
+/* Reduced van der Waals pressure p~(rho~, T~) (section 3). */
+double orc_vdw_reduced(double rr, double Tr);
+
+/* Maxwell equal-chemical-potential coexistence at reduced temperature Tr in (0,1):
+ * reduced vapour density, liquid density and saturation pressure. */
+int orc_maxwell(double Tr, double* rv, double* rl, double* psat);
+
+/* Equilibrium populations (eq:feq) of a lattice at density rho and velocity u[3]. */
+int orc_equilibrium(int Q, double rho, const double* u, double* feq);
+
+/* Isotropic pseudopotential force of section 3 from a field Phi on a periodic box. */
+int orc_force(int Q, int nx, int ny, int nz, double A, const double* Phi, double* F);
+
+/* Central-difference divergence of a vector field (3 planes) on a periodic box. */
+int orc_divergence(int D, int nx, int ny, int nz, const double* u, double* div);
+
+/* Conservative heat-conduction increment div(lambda grad T) per unit time,
+ * lambda = rho c_v chi, face conductivity = arithmetic mean of the two nodes. */
+int orc_conduction(int D, int nx, int ny, int nz, double c_v, double chi,
+                   const double* rho, const double* T, double* out);
+
+typedef struct orc_sim orc_sim;
+
+/* Equilibrium initial state N = Neq(rho0,u0), g = geq(rho0 c_v T0, u0).
+ * Returns NULL and *status = ORC_EINVAL on bad parameters or fields. */
+orc_sim* orc_create(const orc_params* p, const double* rho0, const double* u0,
+                    const double* T0, int* status);
+/* Advance nsteps time steps; returns ORC_OK or ORC_EUNSTABLE (state is left at
+ * the failing step). */
+int orc_step(orc_sim* s, int nsteps);
+/* rho, u* (eq:ustar, 3 planes), E, T of the current state.  Any pointer may be NULL. */
+int orc_moments(orc_sim* s, double* rho, double* ustar, double* E, double* T);
+/* Totals in index order: mass, momentum x,y,z, internal energy. */
+void orc_totals(orc_sim* s, double* out5);
+/* Energy-source fields of the last step: work, conduction, latent (each n values). */
+void orc_last_sources(orc_sim* s, double* work, double* cond, double* latent);
+/* Copy populations out / in, k-major planes: f[k*n + idx]. */
+void orc_get_pops(orc_sim* s, double* N, double* g);
+void orc_set_pops(orc_sim* s, const double* N, const double* g);
+long long orc_step_count(orc_sim* s);
+void orc_free(orc_sim* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
