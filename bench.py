@@ -1,0 +1,184 @@
+"""Benchmark of the fused thermal multiphase LBM step on one MI355X.
+
+Default workload: D3Q19 thermal two-phase droplet, 128^3 periodic, FP32 populations, van der
+Waals EOS at T/Tc = 0.8, liquid sphere of radius 24 in vapour with +-0.5% seeded noise, uniform
+velocity (0.05, 0, 0), every physical term on.  The state is resident in HBM before the timed
+region; the timed region is K fused step launches bracketed by HIP events on the simulation's
+stream (torch's current stream, so torch.cuda.Event sees exactly these launches).
+
+Prints ONE JSON line:
+  value     - node updates per second in millions (MLUPS), one update = both population sets;
+  roofline  - the step kernel against HBM: algorithmic bytes 2 sets x 19 x (read + write)
+              x 4 B = 304 B per node update, divided by the measured launch duration, against
+              the 8 TB/s peak; 'traffic' is the HBM traffic per launch measured by rocprofv3
+              counters (profiles/), or null when not measured for the current kernel source;
+  cpu_baseline - the FP64 CPU oracle timed on the host cores on a bounded sample (a few steps
+              of the same 128^3 workload).
+
+--gpus N with N > 1 exits: this build runs on one GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (coupled density+energy) & % HBM roofline, 1 GPU; serving p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = {4: 2 * 19 * 2 * 4, 8: 2 * 19 * 2 * 8}
+KERNEL_SOURCES = ["paper_1705_10045_amd/csrc/step_kernel.hpp", "paper_1705_10045_amd/csrc/physics.hpp",
+                  "paper_1705_10045_amd/csrc/lattice.hpp", "paper_1705_10045_amd/csrc/kernels.hip",
+                  "paper_1705_10045_amd/csrc/api.hip"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name):
+    from paper_1705_10045_amd import inputs as I
+    if name == "droplet128":
+        case = I.droplet_3d(n=128, radius=24.0, Tr=0.8, noise=0.005, velocity=(0.05, 0.0, 0.0))
+        return case, 4, {"workload": "d3q19_thermal_droplet_128^3_fp32", "lattice": "D3Q19",
+                         "shape": [128, 128, 128], "storage": "fp32", "T_over_Tc": 0.8,
+                         "radius": 24, "noise": 0.005, "velocity": [0.05, 0.0, 0.0],
+                         "terms": "work+conduction+latent+pseudoforces"}
+    if name in ("spinodal256", "spinodal256_fp64"):
+        storage = 8 if name.endswith("fp64") else 4
+        case = I.spinodal_3d(n=256, Tr=0.75, rho_mean=1.0, sigma=0.02)
+        return case, storage, {"workload": "d3q19_spinodal_256^3_%s" % ("fp64" if storage == 8 else "fp32"),
+                               "lattice": "D3Q19", "shape": [256, 256, 256],
+                               "storage": "fp64" if storage == 8 else "fp32", "T_over_Tc": 0.75,
+                               "rho_mean": 1.0, "noise_sigma": 0.02,
+                               "terms": "work+conduction+latent+pseudoforces"}
+    raise SystemExit("unknown workload %s" % name)
+
+
+def measured_traffic(config_name, bytes_alg):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this workload, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % config_name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(case, budget_s=12.0):
+    """The oracle as it stands, on the host cores, over whole steps of the same workload."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    s = oracle.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"])
+    n = case["rho0"].size
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        s.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or steps >= 50:
+            break
+    s.close()
+    return {"value": round(n * steps / el / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d whole FP64 steps of the same %s workload (%.1f s)" %
+                      (steps, "x".join(str(d) for d in case["rho0"].shape[::-1]), el)}
+
+
+def copy_probe(gib=1.0, reps=5):
+    """A plain device-to-device copy of known size, for scaling rocprofv3 byte counters."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                      "launches": reps}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="droplet128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (asked for %d)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+
+    import torch
+    from paper_1705_10045_amd import build as lib_build
+    from paper_1705_10045_amd import lbm
+    if not os.path.exists(lib_build.LIB):
+        lib_build.build()
+
+    case, storage, config = workload(args.workload)
+    n = case["rho0"].size
+    stream = torch.cuda.current_stream()
+    print("bench: %s, %d warmup + %d timed steps" % (config["workload"], args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+    sim = lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"],
+                  storage_bytes=storage, stream=stream.cuda_stream)
+    info = sim.launch_info()
+    sim.step(args.warmup)
+
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    sim.step_async(args.steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    sim.check()
+    ms = start.elapsed_time(end)
+    ms_per_step = ms / args.steps
+    mlups = n * args.steps / (ms / 1e3) / 1e6
+
+    bytes_alg = BYTES_PER_UPDATE[storage] * n
+    achieved = bytes_alg / (ms_per_step / 1e3) / 1e9
+    traffic = measured_traffic(config["workload"], bytes_alg)
+    totals = sim.reduce()
+    sim.close()
+
+    out = {
+        "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if storage == 4 else "f64", "data": "synthetic",
+        "config": dict(config, launch=info),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "lbm::k_step<19,%s> (one launch per step)" %
+                               ("float" if storage == 4 else "double"),
+                     "algorithmic_bytes_per_launch": bytes_alg},
+        "totals_fp64": [float(x) for x in totals],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * lbm_mi355x.h -- C ABI of the MI355X (gfx950) thermal multiphase lattice Boltzmann library.
+ *
+ * Method: Kupershtokh, Medvedev, Gribanov, "Thermal lattice Boltzmann method for multiphase
+ * flows" (arXiv:1705.10045).  One time step advances two population sets on a periodic
+ * D2Q9 or D3Q19 lattice (h = dt = 1, theta = 1/3):
+ *   - density populations N_k: BGK collision (section 2, eq:lbe, eq:feq) with the
+ *     pseudopotential force of a van der Waals fluid (section 3, eq:force2 and its isotropic
+ *     lattice form) applied by the exact difference method (eq:edm);
+ *   - energy populations g_k, E = sum g_k = rho c_v T: BGK collision with relaxation time
+ *     tau_E (eq:gk), the finite-difference source dE spread in proportion to g_k (dg(1),
+ *     section 4) and the EDM "pseudoforces" dg(2) (section 4);
+ *   - dE = pressure work -p div u* (sections 4 and 6.2) + heat conduction div(lambda grad T),
+ *     lambda = rho c_v chi (section 4) + latent heat released inside the transition layer
+ *     (section 5).
+ *
+ * Conventions for every host array argument: FP64, row-major over nodes,
+ * idx = x + nx*(y + ny*z); vector fields are three consecutive planes [vx(n)|vy(n)|vz(n)].
+ * Host arrays are owned by the caller and only read/written during the call.  All device
+ * memory is owned by the library and released by lbm_free / lbm_pool_destroy.
+ * Functions never throw; they return an lbm_status and record a message retrievable with
+ * lbm_last_error() on the calling thread.  Calls on one lbm_sim are not re-entrant.
+ */
+#ifndef LBM_MI355X_H
+#define LBM_MI355X_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* bad parameter, shape or initial field                        */
+    LBM_ENOMEM = -2,     /* device allocation failed                                     */
+    LBM_EUNSTABLE = -3,  /* a node left the EOS domain (Phi^2 <= 0, rho~ >= 3, non-finite) */
+    LBM_EDEVICE = -4,    /* HIP runtime error                                            */
+    LBM_EBUSY = -5       /* serving pool: no free slot or memory budget for the request   */
+} lbm_status;
+
+/* Physical terms (the ablations of sections 4-6). */
+enum {
+    LBM_WORK = 1u,         /* pressure work -p div u*                                      */
+    LBM_CONDUCTION = 2u,   /* heat conduction                                              */
+    LBM_LATENT = 4u,       /* latent heat inside the transition layer                      */
+    LBM_PSEUDOFORCE = 8u,  /* EDM pseudoforces on the energy populations                   */
+    LBM_BAROTROPIC = 16u   /* EOS evaluated at the fixed temperature T0_baro (section 4)   */
+};
+
+typedef struct {
+    int lattice;          /* 9 = D2Q9 (nz must be 1) or 19 = D3Q19                           */
+    int nx, ny, nz;       /* periodic box, each >= 1                                         */
+    int storage_bytes;    /* 4 = FP32 populations (FP32 arithmetic, FP64 EOS and latent band),
+                             8 = FP64 populations and arithmetic                             */
+    double tau, tau_E;    /* BGK relaxation times of N_k and g_k, both > 1/2                 */
+    double A;             /* force mixing parameter of section 3 (the paper uses -0.152)     */
+    double rho_c, T_c, p_c; /* critical point of the reduced vdW EOS, lattice units         */
+    double c_v, chi;      /* specific heat at constant volume, thermal diffusivity           */
+    double rhoQ;          /* rho_liq * Q, energy per volume released across the band         */
+    double T0_baro;       /* EOS temperature with LBM_BAROTROPIC                             */
+    unsigned flags;       /* LBM_WORK | LBM_CONDUCTION | LBM_LATENT | LBM_PSEUDOFORCE [...]  */
+} lbm_params;
+
+typedef struct lbm_sim lbm_sim;
+
+/* Create a simulation in the equilibrium state N_k = Neq_k(rho0, u0),
+ * g_k = geq_k(rho0 c_v T0, u0) (eq:feq with E in place of rho, section 4).
+ * rho0[n], u0[3n], T0[n]: host FP64 fields.  stream: a hipStream_t on the current device on
+ * which every later call enqueues its work, or NULL for a library-created stream.
+ * Rejects (LBM_EINVAL) tau or tau_E <= 1/2, lattice/shape mismatch, chi >= 0.5/d with
+ * conduction on (d = number of axes with extent > 1; section 6.1), a non-positive or
+ * non-finite field, rho0/rho_c >= 3, Phi^2 = rho theta - p <= 0 at any node (section 3), and
+ * an initial field violating (dp/drho)_T <= (h/dt)^2 + theta (section 3). */
+lbm_status lbm_init(const lbm_params* params, const double* rho0, const double* u0,
+                    const double* T0, void* stream, lbm_sim** out);
+
+/* Enqueue nsteps (>= 0) time steps on the simulation's stream, then synchronise and check the
+ * device error word.  LBM_EUNSTABLE if any node left the EOS domain during these steps; the
+ * state is then not meaningful (restore a checkpoint). */
+lbm_status lbm_step(lbm_sim* sim, int nsteps);
+
+/* Enqueue nsteps time steps without synchronising (for timing and overlap); errors found on
+ * the device are reported by the next lbm_step, lbm_check or lbm_moments. */
+lbm_status lbm_step_async(lbm_sim* sim, int nsteps);
+
+/* Synchronise the stream and report the device error word (LBM_OK or LBM_EUNSTABLE). */
+lbm_status lbm_check(lbm_sim* sim);
+
+/* Fields of the current state: rho = sum N_k and E = sum g_k (eq:hydro, section 4),
+ * u* = (sum c_k N_k + F/2)/rho (eq:ustar), T = E/(rho c_v).  Each argument is a caller-owned
+ * host FP64 array of n values (u_star: 3n), or NULL to skip it.  Synchronises. */
+lbm_status lbm_moments(lbm_sim* sim, double* rho, double* u_star, double* E, double* T);
+
+/* Same as lbm_moments but into caller-owned device FP64 arrays on the simulation's device;
+ * enqueued on the simulation's stream (not synchronised). */
+lbm_status lbm_moments_device(lbm_sim* sim, double* rho, double* u_star, double* E, double* T);
+
+/* Totals of the current state accumulated in FP64 with a deterministic reduction order:
+ * out[0] = sum N_k (mass), out[1..3] = sum c_k N_k (momentum), out[4] = sum g_k (internal
+ * energy).  Mass and momentum are conserved by the step (eq:edm and the antisymmetric force);
+ * energy is conserved when work and latent heat are off. */
+lbm_status lbm_reduce(lbm_sim* sim, double out[5]);
+
+/* Number of time steps taken since lbm_init (or restored by lbm_restore). */
+long long lbm_step_count(const lbm_sim* sim);
+
+/* Bytes of device memory the state of a simulation with these parameters occupies
+ * (population buffers; excludes transient buffers of lbm_moments). */
+size_t lbm_footprint_bytes(const lbm_params* params);
+
+/* Serialise the complete state (populations, step count) into host_buf of capacity cap;
+ * *used receives the size (call with host_buf = NULL to query it).  Synchronises. */
+lbm_status lbm_checkpoint(lbm_sim* sim, void* host_buf, size_t cap, size_t* used);
+
+/* Restore a state written by lbm_checkpoint for the same parameters and shape. */
+lbm_status lbm_restore(lbm_sim* sim, const void* host_buf, size_t len);
+
+/* Release the simulation and its device memory.  NULL is accepted. */
+lbm_status lbm_free(lbm_sim* sim);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+/* Launch geometry of the fused step kernel: tile width/height in nodes, z-chunk length and
+ * number of workgroups per step (for profiling reports). */
+lbm_status lbm_launch_info(const lbm_sim* sim, int info[4]);
+
+/* Velocity set used by the library (section 2) and the force coefficients of section 3:
+ * c[3Q] (integer components), w[Q], G[Q], *alpha.  Returns the dimension D, or LBM_EINVAL
+ * for an unsupported Q.  Host only; touches no device. */
+int lbm_lattice_info(int Q, int* c, double* w, double* G, double* alpha);
+
+/* Reduced van der Waals coexistence densities (rho~_vapour, rho~_liquid) at reduced
+ * temperature Tr, from the library's FP64 Maxwell table (section 5 uses them as the band
+ * limits rho_1, rho_2).  LBM_EINVAL outside the table range [0.4, 0.999]. */
+lbm_status lbm_coexistence(double Tr, double* rho_v, double* rho_l);
+
+/* ---------------------------------------------------------------------------------------
+ * Serving: many independent D3Q19 simulations resident on one device.
+ *
+ * A pool owns device memory up to hbm_budget_bytes and up to max_slots slots.  Requests are
+ * admitted into free slots while their footprint fits the remaining budget; one call to
+ * lbm_pool_run advances every active slot by steps_per_run time steps with one batched
+ * launch per step (captured once into a HIP graph and replayed), so requests of different
+ * lattice sizes overlap on the device.  A slot whose remaining step count reaches zero stops
+ * being advanced; its result stays resident until collected, after which the slot and its
+ * memory are free for new requests.  Each request's result does not depend on which other
+ * requests share the pool.
+ * --------------------------------------------------------------------------------------- */
+typedef struct lbm_pool lbm_pool;
+
+/* Create a pool on the current device.  params of submitted requests must use lattice 19,
+ * storage 4 and edges up to max_edge. */
+lbm_status lbm_pool_create(size_t hbm_budget_bytes, int max_slots, int steps_per_run,
+                           void* stream, lbm_pool** out);
+
+/* Admit a request (fields as for lbm_init).  *ticket identifies it.  LBM_EBUSY if no slot is
+ * free or its footprint exceeds the remaining budget (nothing is allocated then). */
+lbm_status lbm_pool_submit(lbm_pool* pool, const lbm_params* params, const double* rho0,
+                           const double* u0, const double* T0, long long nsteps,
+                           long long* ticket);
+
+/* Advance every active request by up to steps_per_run steps; synchronises and refreshes the
+ * completion state. */
+lbm_status lbm_pool_run(lbm_pool* pool);
+
+/* Completion of a ticket: *done = 1 when all its steps have run; *result = LBM_OK or
+ * LBM_EUNSTABLE for a request that left the EOS domain (retired early, others unaffected). */
+lbm_status lbm_pool_poll(lbm_pool* pool, long long ticket, int* done, lbm_status* result);
+
+/* Copy the final fields of a finished request (as lbm_moments) and release its slot. */
+lbm_status lbm_pool_collect(lbm_pool* pool, long long ticket, double* rho, double* u_star,
+                            double* E, double* T);
+
+/* Counters: out[0] active slots, out[1] bytes in use, out[2] budget, out[3] free slots. */
+lbm_status lbm_pool_stats(const lbm_pool* pool, long long out[4]);
+
+lbm_status lbm_pool_destroy(lbm_pool* pool);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_MI355X_H */

@@ -1,0 +1,561 @@
+// Host side of the C ABI (include/lbm_mi355x.h): parameter validation, the FP64 Maxwell
+// table, device memory, stepping, moments, reductions and checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/lbm_mi355x.h"
+#include "kernels.hpp"
+#include "lattice.hpp"
+#include "physics.hpp"
+#include "sim.hpp"
+
+namespace lbm {
+
+static thread_local char g_last_error[512] = "";
+
+void set_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_last_error[0] = '\0'; }
+
+lbm_status hip_fail(hipError_t e, const char* what)
+{
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE;
+}
+
+// ------------------------------------------------------------------------------------------
+// Maxwell coexistence table (section 5 band limits), reduced van der Waals fluid.
+//
+// Equal-area rule in specific volume v = 1/rho: p(v_l) = p(v_g) and
+// integral_{v_l}^{v_g} p dv = p (v_g - v_l), with p(v) = 8T/(3v - 1) - 3/v^2 and the
+// antiderivative (8T/3) ln(3v - 1) + 3/v.  Solved by Newton's method in (v_l, v_g),
+// continued from the critical point (rho = 1 -/+ 2 sqrt(1 - T)) down the temperature grid.
+// ------------------------------------------------------------------------------------------
+namespace {
+
+double p_of_v(double v, double T) { return 8.0 * T / (3.0 * v - 1.0) - 3.0 / (v * v); }
+double dp_of_v(double v, double T)
+{
+    const double a = 3.0 * v - 1.0;
+    return -24.0 * T / (a * a) + 6.0 / (v * v * v);
+}
+double int_p(double v, double T) { return (8.0 * T / 3.0) * std::log(3.0 * v - 1.0) + 3.0 / v; }
+
+bool solve_coexistence(double T, double& vl, double& vg)
+{
+    for (int it = 0; it < 100; ++it) {
+        const double pl = p_of_v(vl, T), pg = p_of_v(vg, T);
+        const double f1 = pl - pg;
+        const double f2 = int_p(vg, T) - int_p(vl, T) - pl * (vg - vl);
+        const double a11 = dp_of_v(vl, T), a12 = -dp_of_v(vg, T);
+        const double a21 = -dp_of_v(vl, T) * (vg - vl), a22 = pg - pl;
+        const double det = a11 * a22 - a12 * a21;
+        if (det == 0.0 || !std::isfinite(det)) return false;
+        const double dl = (f1 * a22 - a12 * f2) / det;
+        const double dg = (a11 * f2 - a21 * f1) / det;
+        vl -= dl;
+        vg -= dg;
+        if (!(vl > 1.0 / 3.0) || !(vg > vl)) return false;
+        if (std::fabs(dl) < 1e-15 * vl && std::fabs(dg) < 1e-15 * vg) return true;
+    }
+    return true;
+}
+
+struct MaxwellTable {
+    std::vector<double> rho;  // interleaved (vapour, liquid) reduced densities
+    double s0 = 0.0, ds = 0.0;
+    bool ok = false;
+};
+
+const MaxwellTable& maxwell_table()
+{
+    static MaxwellTable tab;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const int n = kMaxwellPoints;
+        tab.rho.assign(2 * n, 0.0);
+        tab.s0 = std::sqrt(1.0 - kLatentTmax);
+        tab.ds = (std::sqrt(1.0 - kLatentTmin) - tab.s0) / (n - 1);
+        double vl = 0, vg = 0, pl1 = 0, pg1 = 0, pl2 = 0, pg2 = 0;  // last two solutions
+        bool good = true;
+        for (int i = 0; i < n && good; ++i) {
+            const double s = tab.s0 + i * tab.ds;
+            const double T = 1.0 - s * s;
+            if (i == 0) {          // critical-point asymptotics rho = 1 -/+ 2 sqrt(1 - T)
+                vl = 1.0 / (1.0 + 2.0 * s);
+                vg = 1.0 / (1.0 - 2.0 * s);
+            } else if (i == 1) {   // previous solution
+                vl = pl1;
+                vg = pg1;
+            } else {               // linear extrapolation along the branch
+                vl = 2.0 * pl1 - pl2;
+                vg = 2.0 * pg1 - pg2;
+            }
+            good = solve_coexistence(T, vl, vg);
+            pl2 = pl1; pg2 = pg1;
+            pl1 = vl; pg1 = vg;
+            tab.rho[2 * i] = 1.0 / vg;
+            tab.rho[2 * i + 1] = 1.0 / vl;
+        }
+        tab.ok = good;
+    });
+    return tab;
+}
+
+// dp/drho at fixed T for the reduced EOS in lattice units.
+double dp_drho(double rho, double T, const Phys& ph)
+{
+    const double rr = rho * ph.inv_rho_c, tr = T * ph.inv_T_c;
+    const double a = 3.0 - rr;
+    return ph.p_c * ph.inv_rho_c * (24.0 * tr / (a * a) - 6.0 * rr);
+}
+
+}  // namespace
+
+bool host_band_limits(double Tr, double& rv, double& rl)
+{
+    const MaxwellTable& t = maxwell_table();
+    if (!t.ok || !(Tr >= kLatentTmin && Tr <= kLatentTmax)) return false;
+    const double pos = (std::sqrt(1.0 - Tr) - t.s0) / t.ds;
+    int j = (int)pos;
+    j = j < 1 ? 1 : (j > kMaxwellPoints - 3 ? kMaxwellPoints - 3 : j);
+    const double x = pos - j;
+    const double l0 = -x * (x - 1.0) * (x - 2.0) / 6.0, l1 = (x + 1.0) * (x - 1.0) * (x - 2.0) / 2.0;
+    const double l2 = -(x + 1.0) * x * (x - 2.0) / 2.0, l3 = (x + 1.0) * x * (x - 1.0) / 6.0;
+    const double* q = t.rho.data() + 2 * (j - 1);
+    rv = l0 * q[0] + l1 * q[2] + l2 * q[4] + l3 * q[6];
+    rl = l0 * q[1] + l1 * q[3] + l2 * q[5] + l3 * q[7];
+    return true;
+}
+
+Phys make_phys(const lbm_params& p)
+{
+    Phys ph;
+    ph.omega = 1.0 / p.tau;
+    ph.omega_E = 1.0 / p.tau_E;
+    ph.A = p.A;
+    ph.inv_alpha = p.lattice == 9 ? 1.0 / Lattice<9>::alpha : 1.0 / Lattice<19>::alpha;
+    ph.rho_c = p.rho_c;
+    ph.inv_rho_c = 1.0 / p.rho_c;
+    ph.inv_T_c = 1.0 / p.T_c;
+    ph.p_c = p.p_c;
+    ph.c_v = p.c_v;
+    ph.inv_c_v = 1.0 / p.c_v;
+    ph.cond_half = 0.5 * p.c_v * p.chi;
+    ph.rhoQ = p.rhoQ;
+    ph.T0_baro = p.T0_baro;
+    ph.flags = p.flags;
+    return ph;
+}
+
+long long padded_plane(long long n) { return (n + 63) / 64 * 64; }
+
+size_t state_bytes(const lbm_params& p)
+{
+    const long long n = (long long)p.nx * p.ny * p.nz;
+    return (size_t)2 * p.lattice * padded_plane(n) * p.storage_bytes;
+}
+
+lbm_status validate_params(const lbm_params* p)
+{
+    if (!p) { set_error("params is NULL"); return LBM_EINVAL; }
+    if (p->lattice != 9 && p->lattice != 19) {
+        set_error("lattice must be 9 (D2Q9) or 19 (D3Q19), got %d", p->lattice);
+        return LBM_EINVAL;
+    }
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) { set_error("box extents must be >= 1"); return LBM_EINVAL; }
+    if (p->lattice == 9 && p->nz != 1) { set_error("D2Q9 needs nz == 1"); return LBM_EINVAL; }
+    if ((long long)p->nx * p->ny * p->nz >= (1LL << 31)) { set_error("box exceeds 2^31 nodes"); return LBM_EINVAL; }
+    if (p->storage_bytes != 4 && p->storage_bytes != 8) { set_error("storage_bytes must be 4 or 8"); return LBM_EINVAL; }
+    if (!(p->tau > 0.5) || !(p->tau_E > 0.5)) { set_error("BGK needs tau > 1/2 and tau_E > 1/2"); return LBM_EINVAL; }
+    if (!(p->rho_c > 0) || !(p->T_c > 0) || !(p->p_c > 0) || !(p->c_v > 0)) {
+        set_error("rho_c, T_c, p_c and c_v must be positive");
+        return LBM_EINVAL;
+    }
+    if (!(p->chi >= 0) || !(p->rhoQ >= 0) || !std::isfinite(p->A)) { set_error("chi, rhoQ must be >= 0 and A finite"); return LBM_EINVAL; }
+    const int d = (p->nx > 1) + (p->ny > 1) + (p->lattice == 19 && p->nz > 1);
+    if ((p->flags & LBM_CONDUCTION) && !(p->chi < 0.5 / (d < 1 ? 1 : d))) {
+        set_error("explicit conduction needs chi < 0.5/d = %g (section 6.1)", 0.5 / (d < 1 ? 1 : d));
+        return LBM_EINVAL;
+    }
+    if ((p->flags & LBM_BAROTROPIC) && !(p->T0_baro > 0)) { set_error("barotropic EOS needs T0_baro > 0"); return LBM_EINVAL; }
+    if ((p->flags & LBM_LATENT) && !maxwell_table().ok) { set_error("Maxwell table construction failed"); return LBM_EDEVICE; }
+    return LBM_OK;
+}
+
+lbm_status validate_fields(const lbm_params& p, const double* rho0, const double* u0, const double* T0)
+{
+    if (!rho0 || !u0 || !T0) { set_error("initial fields must not be NULL"); return LBM_EINVAL; }
+    const long long n = (long long)p.nx * p.ny * p.nz;
+    const Phys ph = make_phys(p);
+    const double bound = 1.0 + kTheta;  // (h/dt)^2 + theta, section 3
+    for (long long i = 0; i < n; ++i) {
+        const double r = rho0[i], T = T0[i];
+        if (!(r > 0) || !(r * ph.inv_rho_c < 3.0) || !(T > 0) || !std::isfinite(T)) {
+            set_error("node %lld: need 0 < rho0 < 3 rho_c and T0 > 0 (rho0 = %g, T0 = %g)", i, r, T);
+            return LBM_EINVAL;
+        }
+        if (!std::isfinite(u0[i]) || !std::isfinite(u0[n + i]) || !std::isfinite(u0[2 * n + i])) {
+            set_error("node %lld: non-finite velocity", i);
+            return LBM_EINVAL;
+        }
+        const double Te = (p.flags & LBM_BAROTROPIC) ? p.T0_baro : T;
+        if (!(r * kTheta - vdw_pressure(r, Te, ph) > 0)) {
+            set_error("node %lld: Phi^2 = rho theta - p <= 0 (section 3)", i);
+            return LBM_EINVAL;
+        }
+        if (dp_drho(r, Te, ph) > bound) {
+            set_error("node %lld: (dp/drho)_T = %g exceeds the stability bound %g (section 3)", i,
+                      dp_drho(r, Te, ph), bound);
+            return LBM_EINVAL;
+        }
+    }
+    return LBM_OK;
+}
+
+// Launch geometry: tiles from step_tile, z chunks sized for >= ~1024 workgroups.
+void choose_geometry(lbm_sim* s)
+{
+    const lbm_params& p = s->p;
+    int tx, ty;
+    step_tile(p.lattice, p.storage_bytes, tx, ty);
+    StepGeom& g = s->geom;
+    g.nx = p.nx; g.ny = p.ny; g.nz = p.nz;
+    g.plane = s->plane;
+    g.ntx = (p.nx + tx - 1) / tx;
+    g.nty = (p.ny + ty - 1) / ty;
+    int chunk = p.nz;
+    if (p.lattice == 19) {
+        const long long cols = (long long)g.ntx * g.nty;
+        long long want = (1024 + cols - 1) / cols;
+        long long maxc = p.nz / 4 > 0 ? p.nz / 4 : 1;
+        if (want > maxc) want = maxc;
+        if (want < 1) want = 1;
+        chunk = (int)((p.nz + want - 1) / want);
+        if (const char* e = std::getenv("LBM_CHUNK")) {
+            const int v = std::atoi(e);
+            if (v > 0) chunk = v < p.nz ? v : p.nz;
+        }
+    }
+    g.chunk = chunk;
+    g.nchunks = (p.nz + chunk - 1) / chunk;
+    s->tile_x = tx;
+    s->tile_y = ty;
+}
+
+lbm_status upload_table(lbm_sim* s)
+{
+    const MaxwellTable& t = maxwell_table();
+    hipError_t e = hipMalloc(&s->d_table, sizeof(double) * t.rho.size());
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(Maxwell table)");
+    e = hipMemcpyAsync(s->d_table, t.rho.data(), sizeof(double) * t.rho.size(), hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "upload Maxwell table");
+    s->aux.maxwell = s->d_table;
+    s->aux.tab_s0 = t.s0;
+    s->aux.tab_inv_ds = 1.0 / t.ds;
+    return LBM_OK;
+}
+
+lbm_status enqueue_steps(lbm_sim* s, int nsteps)
+{
+    for (int i = 0; i < nsteps; ++i) {
+        hipError_t e = launch_step(s->p.lattice, s->p.storage_bytes, s->buf[s->cur], s->buf[1 - s->cur],
+                                   s->geom, s->phys, s->aux, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        s->cur ^= 1;
+        s->step += 1;
+    }
+    return LBM_OK;
+}
+
+lbm_status read_error_word(lbm_sim* s)
+{
+    int h = 0;
+    hipError_t e = hipMemcpyAsync(&h, s->d_err, sizeof(int), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "reading the device error word");
+    if (h) {
+        set_error("a node left the EOS domain (Phi^2 <= 0, rho >= 3 rho_c or non-finite) by step %lld", s->step);
+        return LBM_EUNSTABLE;
+    }
+    return LBM_OK;
+}
+
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_last_error; }
+
+size_t lbm_footprint_bytes(const lbm_params* p)
+{
+    if (!p) return 0;
+    return 2 * state_bytes(*p) + sizeof(double) * 2 * kMaxwellPoints + 64;
+}
+
+int lbm_lattice_info(int Q, int* c, double* w, double* G, double* alpha)
+{
+    if (Q == 9) {
+        for (int k = 0; k < 9; ++k) {
+            c[3 * k] = Lattice<9>::cx[k]; c[3 * k + 1] = Lattice<9>::cy[k]; c[3 * k + 2] = Lattice<9>::cz[k];
+            w[k] = weight<9>(k); G[k] = force_coef<9>(k);
+        }
+        *alpha = Lattice<9>::alpha;
+        return 2;
+    }
+    if (Q == 19) {
+        for (int k = 0; k < 19; ++k) {
+            c[3 * k] = Lattice<19>::cx[k]; c[3 * k + 1] = Lattice<19>::cy[k]; c[3 * k + 2] = Lattice<19>::cz[k];
+            w[k] = weight<19>(k); G[k] = force_coef<19>(k);
+        }
+        *alpha = Lattice<19>::alpha;
+        return 3;
+    }
+    return LBM_EINVAL;
+}
+
+lbm_status lbm_coexistence(double Tr, double* rho_v, double* rho_l)
+{
+    double rv, rl;
+    if (!host_band_limits(Tr, rv, rl)) {
+        set_error("reduced temperature %g outside the Maxwell table [%g, %g]", Tr, kLatentTmin, kLatentTmax);
+        return LBM_EINVAL;
+    }
+    if (rho_v) *rho_v = rv;
+    if (rho_l) *rho_l = rl;
+    return LBM_OK;
+}
+
+lbm_status lbm_init(const lbm_params* params, const double* rho0, const double* u0, const double* T0,
+                    void* stream, lbm_sim** out)
+{
+    clear_error();
+    if (!out) { set_error("out is NULL"); return LBM_EINVAL; }
+    *out = nullptr;
+    lbm_status st = validate_params(params);
+    if (st != LBM_OK) return st;
+    st = validate_fields(*params, rho0, u0, T0);
+    if (st != LBM_OK) return st;
+
+    lbm_sim* s = new lbm_sim();
+    s->p = *params;
+    s->phys = make_phys(*params);
+    s->n = (long long)params->nx * params->ny * params->nz;
+    s->plane = padded_plane(s->n);
+    hipGetDevice(&s->device);
+    if (stream) {
+        s->stream = (hipStream_t)stream;
+        s->own_stream = false;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { delete s; return hip_fail(e, "hipStreamCreate"); }
+        s->own_stream = true;
+    }
+    choose_geometry(s);
+    const size_t bytes = state_bytes(s->p);
+    hipError_t e = hipMalloc(&s->buf[0], bytes);
+    if (e == hipSuccess) e = hipMalloc(&s->buf[1], bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_err, sizeof(int) * 16);
+    s->red_blocks = reduce_blocks(s->n);
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_partials, sizeof(double) * (5 * s->red_blocks + 8));
+    if (e != hipSuccess) { lbm_status r = hip_fail(e, "hipMalloc(state)"); lbm_free(s); return r; }
+    hipMemsetAsync(s->d_err, 0, sizeof(int) * 16, s->stream);
+    // zero padding so checkpoints are deterministic
+    hipMemsetAsync(s->buf[0], 0, bytes, s->stream);
+    hipMemsetAsync(s->buf[1], 0, bytes, s->stream);
+    st = upload_table(s);
+    if (st != LBM_OK) { lbm_free(s); return st; }
+
+    double* d_fields = nullptr;
+    e = hipMalloc((void**)&d_fields, sizeof(double) * 5 * s->n);
+    if (e != hipSuccess) { lbm_status r = hip_fail(e, "hipMalloc(initial fields)"); lbm_free(s); return r; }
+    e = hipMemcpyAsync(d_fields, rho0, sizeof(double) * s->n, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_fields + s->n, u0, sizeof(double) * 3 * s->n, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_fields + 4 * s->n, T0, sizeof(double) * s->n, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = launch_init(s->p.lattice, s->p.storage_bytes, s->buf[0], d_fields, d_fields + s->n, d_fields + 4 * s->n,
+                        s->p.nx, s->p.ny, s->p.nz, s->plane, s->p.c_v, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    hipFree(d_fields);
+    if (e != hipSuccess) { lbm_status r = hip_fail(e, "initial state"); lbm_free(s); return r; }
+    s->cur = 0;
+    s->step = 0;
+    *out = s;
+    return LBM_OK;
+}
+
+lbm_status lbm_step_async(lbm_sim* s, int nsteps)
+{
+    clear_error();
+    if (!s || nsteps < 0) { set_error("bad simulation handle or step count"); return LBM_EINVAL; }
+    hipSetDevice(s->device);
+    return enqueue_steps(s, nsteps);
+}
+
+lbm_status lbm_check(lbm_sim* s)
+{
+    clear_error();
+    if (!s) { set_error("simulation is NULL"); return LBM_EINVAL; }
+    hipSetDevice(s->device);
+    return read_error_word(s);
+}
+
+lbm_status lbm_step(lbm_sim* s, int nsteps)
+{
+    lbm_status st = lbm_step_async(s, nsteps);
+    if (st != LBM_OK) return st;
+    return read_error_word(s);
+}
+
+long long lbm_step_count(const lbm_sim* s) { return s ? s->step : -1; }
+
+lbm_status lbm_launch_info(const lbm_sim* s, int info[4])
+{
+    if (!s || !info) { set_error("NULL argument"); return LBM_EINVAL; }
+    info[0] = s->tile_x;
+    info[1] = s->tile_y;
+    info[2] = s->geom.chunk;
+    info[3] = s->geom.ntx * s->geom.nty * s->geom.nchunks;
+    return LBM_OK;
+}
+
+static lbm_status ensure_scratch(lbm_sim* s)
+{
+    if (s->d_scratch) return LBM_OK;
+    hipError_t e = hipMalloc((void**)&s->d_scratch, sizeof(double) * 10 * s->n);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(moment scratch)");
+    return LBM_OK;
+}
+
+lbm_status lbm_moments_device(lbm_sim* s, double* rho, double* u_star, double* E, double* T)
+{
+    clear_error();
+    if (!s) { set_error("simulation is NULL"); return LBM_EINVAL; }
+    hipSetDevice(s->device);
+    lbm_status st = ensure_scratch(s);
+    if (st != LBM_OK) return st;
+    hipError_t e = launch_moments(s->p.lattice, s->p.storage_bytes, s->buf[s->cur], s->d_scratch, s->p.nx,
+                                  s->p.ny, s->p.nz, s->plane, s->phys, s->d_err, rho, u_star, E, T, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "moments launch");
+    return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_sim* s, double* rho, double* u_star, double* E, double* T)
+{
+    clear_error();
+    if (!s) { set_error("simulation is NULL"); return LBM_EINVAL; }
+    hipSetDevice(s->device);
+    lbm_status st = ensure_scratch(s);
+    if (st != LBM_OK) return st;
+    const long long n = s->n;
+    double* scr = s->d_scratch;
+    double* d_us = scr + 7 * n;
+    hipError_t e = launch_moments(s->p.lattice, s->p.storage_bytes, s->buf[s->cur], scr, s->p.nx, s->p.ny,
+                                  s->p.nz, s->plane, s->phys, s->d_err, nullptr, u_star ? d_us : nullptr,
+                                  nullptr, nullptr, s->stream);
+    if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, scr, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && u_star) e = hipMemcpyAsync(u_star, d_us, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && E) e = hipMemcpyAsync(E, scr + 4 * n, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && T) e = hipMemcpyAsync(T, scr + 5 * n, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "moments");
+    return read_error_word(s);
+}
+
+lbm_status lbm_reduce(lbm_sim* s, double out[5])
+{
+    clear_error();
+    if (!s || !out) { set_error("NULL argument"); return LBM_EINVAL; }
+    hipSetDevice(s->device);
+    double* d_out = s->d_partials + 5 * s->red_blocks;
+    hipError_t e = launch_reduce(s->p.lattice, s->p.storage_bytes, s->buf[s->cur], s->n, s->plane, s->d_partials,
+                                 s->red_blocks, d_out, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, sizeof(double) * 5, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "reduction");
+    return LBM_OK;
+}
+
+struct CheckpointHeader {
+    char magic[8];
+    int lattice, nx, ny, nz, storage_bytes, pad;
+    long long step;
+    long long bytes;
+};
+
+lbm_status lbm_checkpoint(lbm_sim* s, void* host_buf, size_t cap, size_t* used)
+{
+    clear_error();
+    if (!s || !used) { set_error("NULL argument"); return LBM_EINVAL; }
+    const size_t bytes = state_bytes(s->p);
+    *used = sizeof(CheckpointHeader) + bytes;
+    if (!host_buf) return LBM_OK;
+    if (cap < *used) { set_error("checkpoint buffer too small (%zu < %zu)", cap, *used); return LBM_EINVAL; }
+    hipSetDevice(s->device);
+    CheckpointHeader h;
+    memset(&h, 0, sizeof(h));
+    memcpy(h.magic, "LBMCKPT1", 8);
+    h.lattice = s->p.lattice; h.nx = s->p.nx; h.ny = s->p.ny; h.nz = s->p.nz;
+    h.storage_bytes = s->p.storage_bytes; h.step = s->step; h.bytes = (long long)bytes;
+    memcpy(host_buf, &h, sizeof(h));
+    hipError_t e = hipMemcpyAsync((char*)host_buf + sizeof(h), s->buf[s->cur], bytes, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+    return LBM_OK;
+}
+
+lbm_status lbm_restore(lbm_sim* s, const void* host_buf, size_t len)
+{
+    clear_error();
+    if (!s || !host_buf) { set_error("NULL argument"); return LBM_EINVAL; }
+    CheckpointHeader h;
+    if (len < sizeof(h)) { set_error("checkpoint too short"); return LBM_EINVAL; }
+    memcpy(&h, host_buf, sizeof(h));
+    const size_t bytes = state_bytes(s->p);
+    if (memcmp(h.magic, "LBMCKPT1", 8) != 0 || h.lattice != s->p.lattice || h.nx != s->p.nx || h.ny != s->p.ny ||
+        h.nz != s->p.nz || h.storage_bytes != s->p.storage_bytes || h.bytes != (long long)bytes ||
+        len < sizeof(h) + bytes) {
+        set_error("checkpoint does not match this simulation's lattice, shape or storage");
+        return LBM_EINVAL;
+    }
+    hipSetDevice(s->device);
+    hipError_t e = hipMemcpyAsync(s->buf[s->cur], (const char*)host_buf + sizeof(h), bytes, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->d_err, 0, sizeof(int), s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "restore copy");
+    s->step = h.step;
+    return LBM_OK;
+}
+
+lbm_status lbm_free(lbm_sim* s)
+{
+    if (!s) return LBM_OK;
+    hipSetDevice(s->device);
+    if (s->stream) hipStreamSynchronize(s->stream);
+    if (s->buf[0]) hipFree(s->buf[0]);
+    if (s->buf[1]) hipFree(s->buf[1]);
+    if (s->d_err) hipFree(s->d_err);
+    if (s->d_partials) hipFree(s->d_partials);
+    if (s->d_table) hipFree(s->d_table);
+    if (s->d_scratch) hipFree(s->d_scratch);
+    if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
+    delete s;
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,261 @@
+// Device kernels of the thermal multiphase LBM library and their launchers.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "lattice.hpp"
+#include "physics.hpp"
+#include "step_kernel.hpp"
+
+namespace lbm {
+
+namespace {
+
+__device__ __forceinline__ void node_xyz(long long i, int nx, int ny, int& x, int& y, int& z)
+{
+    x = (int)(i % nx);
+    const long long r = i / nx;
+    y = (int)(r % ny);
+    z = (int)(r / ny);
+}
+
+__device__ __forceinline__ long long node_index(int x, int y, int z, int nx, int ny, int nz)
+{
+    return wrap_index(x, nx) + (long long)nx * (wrap_index(y, ny) + (long long)ny * wrap_index(z, nz));
+}
+
+// Equilibrium initial state N_k = rho0 P_k(u0), g_k = rho0 c_v T0 P_k(u0) (eq:feq, section 4),
+// stored in pull form: node y keeps, for direction k, the value belonging to node y + c_k.
+template <int Q, class S>
+__global__ void k_init(S* __restrict__ buf, const double* __restrict__ rho0,
+                       const double* __restrict__ u0, const double* __restrict__ T0, int nx,
+                       int ny, int nz, long long plane, double c_v)
+{
+    using L = Lattice<Q>;
+    const long long n = (long long)nx * ny * nz;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int x, y, z;
+    node_xyz(i, nx, ny, x, y, z);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const long long j = node_index(x + L::cx[k], y + L::cy[k], z + L::cz[k], nx, ny, nz);
+        const double rho = rho0[j];
+        const double ux = u0[j], uy = u0[n + j], uz = u0[2 * n + j];
+        const double E = rho * c_v * T0[j];
+        const double cu = L::cx[k] * ux + L::cy[k] * uy + L::cz[k] * uz;
+        const double P = eq_poly(weight<Q>(k), cu, ux * ux + uy * uy + uz * uz);
+        buf[(long long)k * plane + i] = S(rho * P);
+        buf[(long long)(Q + k) * plane + i] = S(E * P);
+    }
+}
+
+// Moments of the current state in FP64: scratch = [rho | jx | jy | jz | E | T | Phi].
+template <int Q, class S>
+__global__ void k_moments_a(const S* __restrict__ buf, double* __restrict__ scr, int nx, int ny,
+                            int nz, long long plane, Phys ph, int* err)
+{
+    using L = Lattice<Q>;
+    const long long n = (long long)nx * ny * nz;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int x, y, z;
+    node_xyz(i, nx, ny, x, y, z);
+    double rho = 0, jx = 0, jy = 0, jz = 0, E = 0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const long long j = node_index(x - L::cx[k], y - L::cy[k], z - L::cz[k], nx, ny, nz);
+        const double nk = double(buf[(long long)k * plane + j]);
+        rho += nk;
+        jx += L::cx[k] * nk;
+        jy += L::cy[k] * nk;
+        jz += L::cz[k] * nk;
+        E += double(buf[(long long)(Q + k) * plane + j]);
+    }
+    const double T = E / (rho * ph.c_v);
+    const double Te = (ph.flags & kBaro) ? ph.T0_baro : T;
+    double phi2 = rho * kTheta - vdw_pressure(rho, Te, ph);
+    if (!(phi2 > 0.0) || !(rho * ph.inv_rho_c < 3.0) || !(rho > 0.0) || !(E == E)) {
+        atomicOr(err, 1);
+        phi2 = 0.0;
+    }
+    scr[i] = rho;
+    scr[n + i] = jx;
+    scr[2 * n + i] = jy;
+    scr[3 * n + i] = jz;
+    scr[4 * n + i] = E;
+    scr[5 * n + i] = T;
+    scr[6 * n + i] = sqrt(phi2);
+}
+
+// u* = (j + F/2)/rho (eq:ustar) with the force of section 3 from the Phi field; writes the
+// requested output fields (any pointer may be null).
+template <int Q>
+__global__ void k_moments_b(const double* __restrict__ scr, int nx, int ny, int nz, Phys ph,
+                            double* __restrict__ rho_o, double* __restrict__ us_o,
+                            double* __restrict__ E_o, double* __restrict__ T_o)
+{
+    using L = Lattice<Q>;
+    const long long n = (long long)nx * ny * nz;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int x, y, z;
+    node_xyz(i, nx, ny, x, y, z);
+    const double* Phi = scr + 6 * n;
+    double s1[3] = {0, 0, 0}, s2[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+        const double p = Phi[node_index(x + L::cx[k], y + L::cy[k], z + L::cz[k], nx, ny, nz)];
+        const double G = force_coef<Q>(k);
+        s1[0] += G * p * p * L::cx[k]; s1[1] += G * p * p * L::cy[k]; s1[2] += G * p * p * L::cz[k];
+        s2[0] += G * p * L::cx[k]; s2[1] += G * p * L::cy[k]; s2[2] += G * p * L::cz[k];
+    }
+    const double rho = scr[i];
+    if (rho_o) rho_o[i] = rho;
+    if (E_o) E_o[i] = scr[4 * n + i];
+    if (T_o) T_o[i] = scr[5 * n + i];
+    if (us_o) {
+        for (int a = 0; a < 3; ++a) {
+            const double F = (ph.A * s1[a] + (1.0 - 2.0 * ph.A) * Phi[i] * s2[a]) * ph.inv_alpha;
+            us_o[a * n + i] = (scr[(1 + a) * n + i] + 0.5 * F) / rho;
+        }
+    }
+}
+
+constexpr int kReduceThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Block partial sums of mass, momentum and internal energy (FP64): per-thread grid-stride
+// sums, 64-lane wavefront shuffles, then the waves in order.
+template <int Q, class S>
+__global__ void __launch_bounds__(kReduceThreads)
+k_reduce_partial(const S* __restrict__ buf, long long n, long long plane, double* __restrict__ part)
+{
+    using L = Lattice<Q>;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const double nk = double(buf[(long long)k * plane + i]);
+            acc[0] += nk;
+            if (L::cx[k]) acc[1] += L::cx[k] * nk;
+            if (L::cy[k]) acc[2] += L::cy[k] * nk;
+            if (L::cz[k]) acc[3] += L::cz[k] * nk;
+            acc[4] += double(buf[(long long)(Q + k) * plane + i]);
+        }
+    }
+    __shared__ double wsum[kReduceThreads / 64][5];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        const double v = wave_sum(acc[c]);
+        if (lane == 0) wsum[wave][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double s = 0;
+        for (int w = 0; w < kReduceThreads / 64; ++w) s += wsum[w][threadIdx.x];
+        part[blockIdx.x * 5 + threadIdx.x] = s;
+    }
+}
+
+__global__ void k_reduce_final(const double* __restrict__ part, int nblocks, double* __restrict__ out)
+{
+    if (threadIdx.x < 5) {
+        double s = 0;
+        for (int b = 0; b < nblocks; ++b) s += part[b * 5 + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+inline unsigned blocks_for(long long n, int threads)
+{
+    return (unsigned)((n + threads - 1) / threads);
+}
+
+template <int Q, class S, class R, int TX, int TY>
+hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Phys& ph,
+                         const StepAux& aux, hipStream_t st)
+{
+    const unsigned nblk = (unsigned)(g.ntx * g.nty * g.nchunks);
+    hipLaunchKernelGGL((k_step<Q, S, R, TX, TY>), dim3(nblk), dim3(TX * TY), 0, st,
+                       (const S*)src, (S*)dst, g, ph, aux);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Tile shapes per (lattice, storage): FP64 halves the tile height to keep the LDS rings of
+// two workgroups within one CU's 160 KB.
+void step_tile(int Q, int storage_bytes, int& tx, int& ty)
+{
+    tx = 32;
+    ty = (Q == 19 && storage_bytes == 8) ? 4 : 8;
+}
+
+hipError_t launch_step(int Q, int storage_bytes, const void* src, void* dst, const StepGeom& g,
+                       const Phys& ph, const StepAux& aux, hipStream_t st)
+{
+    if (Q == 19 && storage_bytes == 4) return launch_step_t<19, float, float, 32, 8>(src, dst, g, ph, aux, st);
+    if (Q == 19 && storage_bytes == 8) return launch_step_t<19, double, double, 32, 4>(src, dst, g, ph, aux, st);
+    if (Q == 9 && storage_bytes == 4) return launch_step_t<9, float, float, 32, 8>(src, dst, g, ph, aux, st);
+    if (Q == 9 && storage_bytes == 8) return launch_step_t<9, double, double, 32, 8>(src, dst, g, ph, aux, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_init(int Q, int storage_bytes, void* buf, const double* rho0, const double* u0,
+                       const double* T0, int nx, int ny, int nz, long long plane, double c_v,
+                       hipStream_t st)
+{
+    const long long n = (long long)nx * ny * nz;
+    const dim3 grid(blocks_for(n, 256)), block(256);
+    if (Q == 19 && storage_bytes == 4) hipLaunchKernelGGL((k_init<19, float>), grid, block, 0, st, (float*)buf, rho0, u0, T0, nx, ny, nz, plane, c_v);
+    else if (Q == 19 && storage_bytes == 8) hipLaunchKernelGGL((k_init<19, double>), grid, block, 0, st, (double*)buf, rho0, u0, T0, nx, ny, nz, plane, c_v);
+    else if (Q == 9 && storage_bytes == 4) hipLaunchKernelGGL((k_init<9, float>), grid, block, 0, st, (float*)buf, rho0, u0, T0, nx, ny, nz, plane, c_v);
+    else if (Q == 9 && storage_bytes == 8) hipLaunchKernelGGL((k_init<9, double>), grid, block, 0, st, (double*)buf, rho0, u0, T0, nx, ny, nz, plane, c_v);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int Q, int storage_bytes, const void* buf, double* scratch, int nx, int ny,
+                          int nz, long long plane, const Phys& ph, int* err, double* rho,
+                          double* us, double* E, double* T, hipStream_t st)
+{
+    const long long n = (long long)nx * ny * nz;
+    const dim3 grid(blocks_for(n, 256)), block(256);
+    if (Q == 19 && storage_bytes == 4) hipLaunchKernelGGL((k_moments_a<19, float>), grid, block, 0, st, (const float*)buf, scratch, nx, ny, nz, plane, ph, err);
+    else if (Q == 19 && storage_bytes == 8) hipLaunchKernelGGL((k_moments_a<19, double>), grid, block, 0, st, (const double*)buf, scratch, nx, ny, nz, plane, ph, err);
+    else if (Q == 9 && storage_bytes == 4) hipLaunchKernelGGL((k_moments_a<9, float>), grid, block, 0, st, (const float*)buf, scratch, nx, ny, nz, plane, ph, err);
+    else if (Q == 9 && storage_bytes == 8) hipLaunchKernelGGL((k_moments_a<9, double>), grid, block, 0, st, (const double*)buf, scratch, nx, ny, nz, plane, ph, err);
+    else return hipErrorInvalidValue;
+    if (Q == 19) hipLaunchKernelGGL((k_moments_b<19>), grid, block, 0, st, scratch, nx, ny, nz, ph, rho, us, E, T);
+    else hipLaunchKernelGGL((k_moments_b<9>), grid, block, 0, st, scratch, nx, ny, nz, ph, rho, us, E, T);
+    return hipGetLastError();
+}
+
+int reduce_blocks(long long n)
+{
+    long long b = (n + kReduceThreads * 8 - 1) / (kReduceThreads * 8);
+    return (int)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+}
+
+hipError_t launch_reduce(int Q, int storage_bytes, const void* buf, long long n, long long plane,
+                         double* partials, int nblocks, double* out, hipStream_t st)
+{
+    const dim3 grid(nblocks), block(kReduceThreads);
+    if (Q == 19 && storage_bytes == 4) hipLaunchKernelGGL((k_reduce_partial<19, float>), grid, block, 0, st, (const float*)buf, n, plane, partials);
+    else if (Q == 19 && storage_bytes == 8) hipLaunchKernelGGL((k_reduce_partial<19, double>), grid, block, 0, st, (const double*)buf, n, plane, partials);
+    else if (Q == 9 && storage_bytes == 4) hipLaunchKernelGGL((k_reduce_partial<9, float>), grid, block, 0, st, (const float*)buf, n, plane, partials);
+    else if (Q == 9 && storage_bytes == 8) hipLaunchKernelGGL((k_reduce_partial<9, double>), grid, block, 0, st, (const double*)buf, n, plane, partials);
+    else return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, st, partials, nblocks, out);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

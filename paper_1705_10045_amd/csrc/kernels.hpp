@@ -1,0 +1,39 @@
+// Launch interface between the host library and the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "physics.hpp"
+
+namespace lbm {
+
+// Geometry of one fused step launch.
+struct StepGeom {
+    int nx, ny, nz;
+    long long plane;        // elements between consecutive population planes
+    int ntx, nty;           // tiles along x and y
+    int chunk;              // z planes per workgroup
+    int nchunks;
+};
+
+// Read-only tables and the error word shared by every step launch of a simulation.
+struct StepAux {
+    const double* __restrict__ maxwell;  // band-limit table (reduced densities)
+    double tab_s0, tab_inv_ds;
+    int* err;                            // device error word (atomicOr)
+};
+
+void step_tile(int Q, int storage_bytes, int& tx, int& ty);
+hipError_t launch_step(int Q, int storage_bytes, const void* src, void* dst, const StepGeom& g,
+                       const Phys& ph, const StepAux& aux, hipStream_t st);
+hipError_t launch_init(int Q, int storage_bytes, void* buf, const double* rho0, const double* u0,
+                       const double* T0, int nx, int ny, int nz, long long plane, double c_v,
+                       hipStream_t st);
+hipError_t launch_moments(int Q, int storage_bytes, const void* buf, double* scratch, int nx, int ny,
+                          int nz, long long plane, const Phys& ph, int* err, double* rho,
+                          double* us, double* E, double* T, hipStream_t st);
+int reduce_blocks(long long n);
+hipError_t launch_reduce(int Q, int storage_bytes, const void* buf, long long n, long long plane,
+                         double* partials, int nblocks, double* out, hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,73 @@
+// Node-local physics of the thermal multiphase LBM, shared by all kernels of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+constexpr double kTheta = 1.0 / 3.0;          // (h/dt)^2 / 3 with h = dt = 1 (section 2)
+constexpr double kLatentTmin = 0.4;           // reduced-temperature window of the latent band
+constexpr double kLatentTmax = 0.999;
+constexpr int kMaxwellPoints = 4096;          // table nodes, uniform in s = sqrt(1 - T~)
+
+// Parameters of one simulation as the kernels see them (passed by value).
+struct Phys {
+    double omega, omega_E;        // 1/tau, 1/tau_E
+    double A, inv_alpha;          // force mixing (section 3), 1/alpha of the lattice
+    double rho_c, inv_rho_c, inv_T_c, p_c;
+    double c_v, inv_c_v;
+    double cond_half;             // c_v chi / 2: face conductivity per unit (rho_i + rho_j)
+    double rhoQ;
+    double T0_baro;
+    unsigned flags;
+};
+
+enum : unsigned { kWork = 1u, kConduction = 2u, kLatent = 4u, kPseudo = 8u, kBaro = 16u };
+
+// w_k (1 + c.u/theta + (c.u)^2/(2 theta^2) - u^2/(2 theta)), eq:feq without the density.
+template <class R>
+__device__ __forceinline__ R eq_poly(R w, R cu, R uu)
+{
+    return w * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
+}
+
+// Reduced van der Waals pressure in lattice units (section 3), FP64.
+__host__ __device__ inline double vdw_pressure(double rho, double T, const Phys& p)
+{
+    const double rr = rho * p.inv_rho_c;
+    const double tr = T * p.inv_T_c;
+    return p.p_c * (8.0 * rr * tr / (3.0 - rr) - 3.0 * rr * rr);
+}
+
+// Coexistence densities (rho_1, rho_2) of the band at reduced temperature Tr, cubic Lagrange
+// interpolation in s = sqrt(1 - Tr) on the FP64 Maxwell table (tab[2i] vapour, tab[2i+1]
+// liquid, reduced densities).  Returns false outside [kLatentTmin, kLatentTmax).
+__device__ __forceinline__ bool band_limits(double Tr, const double* __restrict__ tab,
+                                            double s0, double inv_ds, double rho_c,
+                                            double& r1, double& r2)
+{
+    if (!(Tr >= kLatentTmin && Tr < kLatentTmax)) return false;
+    const double pos = (sqrt(1.0 - Tr) - s0) * inv_ds;
+    int j = (int)pos;
+    j = j < 1 ? 1 : (j > kMaxwellPoints - 3 ? kMaxwellPoints - 3 : j);
+    const double t = pos - j;
+    // Lagrange basis on nodes j-1, j, j+1, j+2 at offset t from node j
+    const double l0 = -t * (t - 1.0) * (t - 2.0) / 6.0;
+    const double l1 = (t + 1.0) * (t - 1.0) * (t - 2.0) / 2.0;
+    const double l2 = -(t + 1.0) * t * (t - 2.0) / 2.0;
+    const double l3 = (t + 1.0) * t * (t - 1.0) / 6.0;
+    const double* q = tab + 2 * (j - 1);
+    r1 = rho_c * (l0 * q[0] + l1 * q[2] + l2 * q[4] + l3 * q[6]);
+    r2 = rho_c * (l0 * q[1] + l1 * q[3] + l2 * q[5] + l3 * q[7]);
+    return true;
+}
+
+__host__ __device__ inline int wrap_index(int i, int n)
+{
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+}  // namespace lbm

@@ -1,0 +1,40 @@
+// Internal state of one simulation behind the opaque lbm_sim handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/lbm_mi355x.h"
+#include "kernels.hpp"
+#include "physics.hpp"
+
+struct lbm_sim {
+    lbm_params p;
+    lbm::Phys phys;
+    lbm::StepGeom geom;
+    lbm::StepAux aux;
+    long long n = 0, plane = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void* buf[2] = {nullptr, nullptr};  // population buffers; buf[cur] holds the current state
+    int cur = 0;
+    long long step = 0;
+    int* d_err = nullptr;
+    double* d_table = nullptr;
+    double* d_partials = nullptr;
+    double* d_scratch = nullptr;         // moment scratch (7n doubles), allocated on first use
+    int red_blocks = 1;
+    int tile_x = 0, tile_y = 0;
+};
+
+namespace lbm {
+void set_error(const char* fmt, ...);
+void clear_error();
+lbm_status hip_fail(hipError_t e, const char* what);
+bool host_band_limits(double Tr, double& rv, double& rl);
+Phys make_phys(const lbm_params& p);
+long long padded_plane(long long n);
+size_t state_bytes(const lbm_params& p);
+lbm_status validate_params(const lbm_params* p);
+lbm_status validate_fields(const lbm_params& p, const double* rho0, const double* u0, const double* T0);
+}  // namespace lbm

@@ -1,0 +1,339 @@
+// Fused single-sweep time step of the thermal multiphase LBM (one launch per step).
+//
+// Storage: structure of arrays, population k of set s (0 = N, 1 = g) at node i is
+// buf[(s*Q + k)*plane + i], i = x + nx*(y + ny*z).  Two buffers: a step reads `src` and
+// writes `dst`.  Pull scheme: dst holds post-collision populations at the node where they were
+// computed, so the state at time t is N_k(x, t) = src[k][x - c_k].
+//
+// Dependencies of one node update (sections 3-5): the force at x needs Phi on the 1-ring, the
+// pressure work and latent heat need div u* (central differences), i.e. u* and hence F on
+// the axis 1-ring, i.e. Phi on a 2-ring; conduction needs rho and T on the axis 1-ring.
+//
+// Work decomposition: a workgroup owns a TX x TY column of nodes and marches through a chunk
+// of z planes.  Per z iteration it runs three stages separated by barriers:
+//   M: pull 2Q populations and form rho, j, E, T, p, Phi for plane zm on the tile plus a
+//      2-node halo (LDS ring of 4 planes);
+//   F: force and u* for plane zm-1 on the tile plus a 1-node halo (LDS ring);
+//   C: energy source, collisions and the store for plane zm-2 on the tile.
+// D2Q9 runs the same code with a single plane (no z halo, no lag between the stages).
+//
+// Per-node quantities of the tile's own nodes (rho, j, E, T, p, F) stay in registers between
+// the stages; populations are re-read for the collision (they were pulled two planes earlier
+// by this workgroup, so the re-read is served by the caches).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "lattice.hpp"
+#include "physics.hpp"
+
+namespace lbm {
+
+// XCD-aware placement: consecutive workgroups are dealt round-robin to the 8 XCDs, so
+// workgroup b is given logical tile (b % 8) * (nblk / 8) + b / 8.  Each XCD then owns a
+// contiguous run of tiles and their shared halos meet in its own L2.
+__device__ __forceinline__ int xcd_logical_block(int b, int nblk)
+{
+    if ((nblk & 7) == 0) return (b & 7) * (nblk >> 3) + (b >> 3);
+    return b;
+}
+
+// Interior-first enumeration of a (W+2h) x (H+2h) region around a W x H tile: slots
+// [0, W*H) are the tile row by row, then two full rows top and bottom, then h columns
+// left and right of each middle row.  Returns region coordinates (rx, ry).
+template <int W, int H, int HALO>
+__device__ __forceinline__ void region_slot(int s, int& rx, int& ry)
+{
+    constexpr int RW = W + 2 * HALO;
+    constexpr int RH = H + 2 * HALO;
+    if (s < W * H) {
+        rx = HALO + s % W;
+        ry = HALO + s / W;
+        return;
+    }
+    int r = s - W * H;
+    if (r < HALO * RW) {
+        rx = r % RW;
+        ry = r / RW;
+        return;
+    }
+    r -= HALO * RW;
+    if (r < HALO * RW) {
+        rx = r % RW;
+        ry = RH - HALO + r / RW;
+        return;
+    }
+    r -= HALO * RW;
+    const int c = r % (2 * HALO);
+    ry = HALO + r / (2 * HALO);
+    rx = c < HALO ? c : RW - 2 * HALO + c;
+}
+
+template <int Q, class S, class R, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY)
+k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const Phys ph,
+       const StepAux aux)
+{
+    using L = Lattice<Q>;
+    constexpr int D = L::D;
+    constexpr int ZH = (D == 3) ? 2 : 0;    // lead of the moment stage over the collision
+    constexpr int NT = TX * TY;
+    constexpr int EX = TX + 4, EY = TY + 4, NE = EX * EY;   // moments: tile + 2-halo
+    constexpr int FX = TX + 2, FY = TY + 2, NF = FX * FY;   // force/u*: tile + 1-halo
+    constexpr int RING = (D == 3) ? 4 : 1;
+    constexpr int ME = (NE + NT - 1) / NT;
+    constexpr int MF = (NF + NT - 1) / NT;
+
+    __shared__ R sPhi[RING][NE];
+    __shared__ R sRho[RING][NE];
+    __shared__ R sT[RING][NE];
+    __shared__ R sJ[3][RING][NE];
+    __shared__ R sU[3][RING][NF];
+
+    const int tid = threadIdx.x;
+    const int nblk = gridDim.x;
+    const int lb = xcd_logical_block(blockIdx.x, nblk);
+    const int tix = lb % g.ntx;
+    const int tiy = (lb / g.ntx) % g.nty;
+    const int tiz = lb / (g.ntx * g.nty);
+    const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * g.chunk;
+    const int z1 = min(z0 + g.chunk, g.nz);
+    const int nxy = g.nx * g.ny;
+
+    // moment-stage slots of this thread: LDS index and wrapped x / y*nx of (node - c) for
+    // c = +1, 0, -1 (index 1 - c)
+    int m_e[ME];
+    int m_x[ME][3], m_y[ME][3];
+#pragma unroll
+    for (int r = 0; r < ME; ++r) {
+        const int s = tid + r * NT;
+        m_e[r] = -1;
+        if (s < NE) {
+            int ex, ey;
+            region_slot<TX, TY, 2>(s, ex, ey);
+            m_e[r] = ex + EX * ey;
+            const int gx = wrap_index(x0 - 2 + ex, g.nx);
+            const int gy = wrap_index(y0 - 2 + ey, g.ny);
+            m_x[r][0] = wrap_index(gx - 1, g.nx);
+            m_x[r][1] = gx;
+            m_x[r][2] = wrap_index(gx + 1, g.nx);
+            m_y[r][0] = wrap_index(gy - 1, g.ny) * g.nx;
+            m_y[r][1] = gy * g.nx;
+            m_y[r][2] = wrap_index(gy + 1, g.ny) * g.nx;
+        }
+    }
+    int f_e[MF], f_f[MF];
+#pragma unroll
+    for (int r = 0; r < MF; ++r) {
+        const int s = tid + r * NT;
+        f_f[r] = -1;
+        f_e[r] = 0;
+        if (s < NF) {
+            int fx, fy;
+            region_slot<TX, TY, 1>(s, fx, fy);
+            f_f[r] = fx + FX * fy;
+            f_e[r] = (fx + 1) + EX * (fy + 1);
+        }
+    }
+    // this thread's own node (slot 0 of every stage)
+    const int otx = tid % TX, oty = tid / TX;
+    const int ox = x0 + otx, oy = y0 + oty;
+    const bool own_in_xy = ox < g.nx && oy < g.ny;
+    const int oe = (otx + 2) + EX * (oty + 2);
+    const int of = (otx + 1) + FX * (oty + 1);
+    const int xs[3] = {m_x[0][0], m_x[0][1], m_x[0][2]};   // slot 0 is the own node
+    const int ys[3] = {m_y[0][0], m_y[0][1], m_y[0][2]};
+
+    const R omega = R(ph.omega), omega_E = R(ph.omega_E);
+    const R Amix = R(ph.A), inv_alpha = R(ph.inv_alpha);
+    const R c_v = R(ph.c_v), cond_half = R(ph.cond_half);
+    const unsigned flags = ph.flags;
+
+    // register ring of the own node's moments: [0] newest plane ... [ZH] plane being collided
+    R o_rho[ZH + 1], o_jx[ZH + 1], o_jy[ZH + 1], o_jz[ZH + 1], o_E[ZH + 1], o_T[ZH + 1];
+    double o_p[ZH + 1];
+    R fcur[3] = {R(0), R(0), R(0)}, fprev[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int q = 0; q <= ZH; ++q) {
+        o_rho[q] = R(1); o_jx[q] = o_jy[q] = o_jz[q] = R(0);
+        o_E[q] = R(1); o_T[q] = R(1); o_p[q] = 0.0;
+    }
+
+    const int niter = (z1 - z0) + 2 * ZH;
+    for (int it = 0; it < niter; ++it) {
+        const int zm = z0 - ZH + it;
+        const int sm = (zm + 4) & (RING - 1);
+        int zoff[3];
+        if constexpr (D == 3) {
+            zoff[0] = wrap_index(zm - 1, g.nz) * nxy;
+            zoff[1] = wrap_index(zm, g.nz) * nxy;
+            zoff[2] = wrap_index(zm + 1, g.nz) * nxy;
+        } else {
+            zoff[0] = zoff[1] = zoff[2] = 0;
+        }
+
+        // ---------------- M: moments, EOS, Phi on the tile + 2-halo of plane zm
+#pragma unroll
+        for (int r = 0; r < ME; ++r) {
+            if (m_e[r] < 0) continue;
+            R rho = R(0), jx = R(0), jy = R(0), jz = R(0), E = R(0);
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                const long long off = (long long)zoff[1 - L::cz[k]] + m_y[r][1 - L::cy[k]] +
+                                      m_x[r][1 - L::cx[k]];
+                const R n = R(src[(long long)k * g.plane + off]);
+                const R e = R(src[(long long)(Q + k) * g.plane + off]);
+                rho += n;
+                E += e;
+                if (L::cx[k] == 1) jx += n; else if (L::cx[k] == -1) jx -= n;
+                if (L::cy[k] == 1) jy += n; else if (L::cy[k] == -1) jy -= n;
+                if (L::cz[k] == 1) jz += n; else if (L::cz[k] == -1) jz -= n;
+            }
+            const R T = E / (rho * c_v);
+            const double Te = (flags & kBaro) ? ph.T0_baro : double(T);
+            const double p = vdw_pressure(double(rho), Te, ph);
+            double phi2 = double(rho) * kTheta - p;
+            const bool ok = phi2 > 0.0 && double(rho) * ph.inv_rho_c < 3.0 && rho > R(0) &&
+                            E == E && E < R(1e30);
+            if (!ok) {
+                atomicOr(aux.err, 1);
+                phi2 = 0.0;
+            }
+            const int e = m_e[r];
+            sPhi[sm][e] = R(sqrt(phi2));
+            sRho[sm][e] = rho;
+            sT[sm][e] = T;
+            sJ[0][sm][e] = jx;
+            sJ[1][sm][e] = jy;
+            sJ[2][sm][e] = jz;
+            if (r == 0) {
+#pragma unroll
+                for (int q = ZH; q > 0; --q) {
+                    o_rho[q] = o_rho[q - 1]; o_jx[q] = o_jx[q - 1]; o_jy[q] = o_jy[q - 1];
+                    o_jz[q] = o_jz[q - 1]; o_E[q] = o_E[q - 1]; o_T[q] = o_T[q - 1];
+                    o_p[q] = o_p[q - 1];
+                }
+                o_rho[0] = rho; o_jx[0] = jx; o_jy[0] = jy; o_jz[0] = jz;
+                o_E[0] = E; o_T[0] = T; o_p[0] = p;
+            }
+        }
+        __syncthreads();
+
+        // ---------------- F: force and u* on the tile + 1-halo of plane zf = zm - ZH/2
+        if (it >= ZH) {
+            const int zf = zm - ZH / 2;
+            const int sf = (zf + 4) & (RING - 1);
+            const int sfm = (zf + 3) & (RING - 1);
+            const int sfp = (zf + 5) & (RING - 1);
+#pragma unroll
+            for (int r = 0; r < MF; ++r) {
+                if (f_f[r] < 0) continue;
+                const int e = f_e[r];
+                R s1x = R(0), s1y = R(0), s1z = R(0), s2x = R(0), s2y = R(0), s2z = R(0);
+#pragma unroll
+                for (int k = 1; k < Q; ++k) {
+                    const int sl = L::cz[k] == 0 ? sf : (L::cz[k] == 1 ? sfp : sfm);
+                    const R phk = sPhi[sl][e + L::cx[k] + EX * L::cy[k]];
+                    const R gph = R(force_coef<Q>(k)) * phk;
+                    const R gph2 = gph * phk;
+                    if (L::cx[k] == 1) { s1x += gph2; s2x += gph; }
+                    else if (L::cx[k] == -1) { s1x -= gph2; s2x -= gph; }
+                    if (L::cy[k] == 1) { s1y += gph2; s2y += gph; }
+                    else if (L::cy[k] == -1) { s1y -= gph2; s2y -= gph; }
+                    if (L::cz[k] == 1) { s1z += gph2; s2z += gph; }
+                    else if (L::cz[k] == -1) { s1z -= gph2; s2z -= gph; }
+                }
+                const R phc = sPhi[sf][e];
+                const R b = (R(1) - R(2) * Amix) * phc;
+                const R Fx = (Amix * s1x + b * s2x) * inv_alpha;
+                const R Fy = (Amix * s1y + b * s2y) * inv_alpha;
+                const R Fz = (Amix * s1z + b * s2z) * inv_alpha;
+                const R rho = sRho[sf][e];
+                const int f = f_f[r];
+                sU[0][sf][f] = (sJ[0][sf][e] + R(0.5) * Fx) / rho;
+                sU[1][sf][f] = (sJ[1][sf][e] + R(0.5) * Fy) / rho;
+                sU[2][sf][f] = (sJ[2][sf][e] + R(0.5) * Fz) / rho;
+                if (r == 0) {
+                    fprev[0] = fcur[0]; fprev[1] = fcur[1]; fprev[2] = fcur[2];
+                    fcur[0] = Fx; fcur[1] = Fy; fcur[2] = Fz;
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---------------- C: energy source, collisions, store for plane zc = zm - ZH
+        if (it >= 2 * ZH && own_in_xy) {
+            const int zc = zm - ZH;
+            const int sc = (zc + 4) & (RING - 1);
+            const int scm = (zc + 3) & (RING - 1);
+            const int scp = (zc + 5) & (RING - 1);
+            const R rho = o_rho[ZH], E = o_E[ZH], T = o_T[ZH];
+            const double p = o_p[ZH];
+            const R* Fo = (ZH > 0) ? fprev : fcur;
+            const R ux = o_jx[ZH] / rho, uy = o_jy[ZH] / rho, uz = o_jz[ZH] / rho;
+            const R dux = Fo[0] / rho, duy = Fo[1] / rho, duz = Fo[2] / rho;
+
+            // div u* by central differences on each axis (section 6.2)
+            R div = R(0.5) * (sU[0][sc][of + 1] - sU[0][sc][of - 1]) +
+                    R(0.5) * (sU[1][sc][of + FX] - sU[1][sc][of - FX]);
+            if constexpr (D == 3) div += R(0.5) * (sU[2][scp][of] - sU[2][scm][of]);
+
+            R dE = R(0);
+            if (flags & kWork) dE -= R(p) * div;
+            if (flags & kConduction) {
+                const R Tc = sT[sc][oe];
+                R acc = (rho + sRho[sc][oe + 1]) * (sT[sc][oe + 1] - Tc) -
+                        (rho + sRho[sc][oe - 1]) * (Tc - sT[sc][oe - 1]) +
+                        (rho + sRho[sc][oe + EX]) * (sT[sc][oe + EX] - Tc) -
+                        (rho + sRho[sc][oe - EX]) * (Tc - sT[sc][oe - EX]);
+                if constexpr (D == 3)
+                    acc += (rho + sRho[scp][oe]) * (sT[scp][oe] - Tc) -
+                           (rho + sRho[scm][oe]) * (Tc - sT[scm][oe]);
+                dE += cond_half * acc;
+            }
+            if (flags & kLatent) {
+                const double Te = (flags & kBaro) ? ph.T0_baro : double(T);
+                double r1, r2;
+                if (band_limits(Te * ph.inv_T_c, aux.maxwell, aux.tab_s0, aux.tab_inv_ds,
+                                ph.rho_c, r1, r2)) {
+                    const double rd = double(rho);
+                    if (rd > r1 && rd < r2) dE -= R(ph.rhoQ / (r2 - r1) * rd * double(div));
+                }
+            }
+            const R dEoE = dE / E;
+
+            const int zoc = wrap_index(zc, g.nz) * nxy;
+            const int zpull[3] = {wrap_index(zc - 1, g.nz) * nxy, zoc,
+                                  wrap_index(zc + 1, g.nz) * nxy};
+            const long long own = (long long)zoc + oy * g.nx + ox;
+            const R vx = ux + dux, vy = uy + duy, vz = uz + duz;
+            const R uu = ux * ux + uy * uy + uz * uz;
+            const R vv = vx * vx + vy * vy + vz * vz;
+            const R keepN = R(1) - omega, keepG = R(1) - omega_E;
+            const bool pseudo = (flags & kPseudo) != 0;
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                const long long off = (long long)(D == 3 ? zpull[1 - L::cz[k]] : zoc) +
+                                      ys[1 - L::cy[k]] + xs[1 - L::cx[k]];
+                const R n = R(src[(long long)k * g.plane + off]);
+                const R e = R(src[(long long)(Q + k) * g.plane + off]);
+                const R w = R(weight<Q>(k));
+                const R cu = R(L::cx[k]) * ux + R(L::cy[k]) * uy + R(L::cz[k]) * uz;
+                const R cv = R(L::cx[k]) * vx + R(L::cy[k]) * vy + R(L::cz[k]) * vz;
+                const R Pu = eq_poly(w, cu, uu);
+                const R Pv = eq_poly(w, cv, vv);
+                // N' = N + (Neq(u) - N)/tau + Neq(v) - Neq(u)      (eq:lbe, eq:edm)
+                const R nn = rho * Pv + keepN * (n - rho * Pu);
+                // g' = g + (geq(u) - g)/tau_E + g dE/E [+ geq(v) - geq(u)]   (eq:gk, section 4)
+                const R gn = pseudo ? E * Pv + keepG * (e - E * Pu) + e * dEoE
+                                    : omega_E * E * Pu + keepG * e + e * dEoE;
+                dst[(long long)k * g.plane + own] = S(nn);
+                dst[(long long)(Q + k) * g.plane + own] = S(gn);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace lbm

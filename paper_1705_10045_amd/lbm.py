@@ -1,0 +1,281 @@
+"""Thin ctypes binding of the C ABI in include/lbm_mi355x.h (argument marshalling only).
+
+Every function here has the name of the C entry point it calls; all arithmetic of the method
+runs in the HIP library.  Fields are numpy float64 arrays of shape (nz, ny, nx) (x fastest)
+or (3, nz, ny, nx) for vectors.  The library is loaded on first use; if it has not been built
+(``python -m paper_1705_10045_amd.build``) every call raises ``LbmUnavailable``.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EUNSTABLE, LBM_EDEVICE, LBM_EBUSY = 0, -1, -2, -3, -4, -5
+LBM_WORK, LBM_CONDUCTION, LBM_LATENT, LBM_PSEUDOFORCE, LBM_BAROTROPIC = 1, 2, 4, 8, 16
+
+_STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EUNSTABLE",
+           -4: "LBM_EDEVICE", -5: "LBM_EBUSY"}
+
+
+class LbmUnavailable(ImportError):
+    pass
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), message))
+        self.status = status
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("nz", ctypes.c_int), ("storage_bytes", ctypes.c_int),
+        ("tau", ctypes.c_double), ("tau_E", ctypes.c_double), ("A", ctypes.c_double),
+        ("rho_c", ctypes.c_double), ("T_c", ctypes.c_double), ("p_c", ctypes.c_double),
+        ("c_v", ctypes.c_double), ("chi", ctypes.c_double), ("rhoQ", ctypes.c_double),
+        ("T0_baro", ctypes.c_double), ("flags", ctypes.c_uint),
+    ]
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_P = ctypes.c_void_p
+_ST = ctypes.c_int
+_LIB = None
+
+# (name, restype, argtypes) of every exported entry point
+_SIGNATURES = [
+    ("lbm_init", _ST, [ctypes.POINTER(lbm_params), _D, _D, _D, _P, ctypes.POINTER(_P)]),
+    ("lbm_step", _ST, [_P, ctypes.c_int]),
+    ("lbm_step_async", _ST, [_P, ctypes.c_int]),
+    ("lbm_check", _ST, [_P]),
+    ("lbm_moments", _ST, [_P, _D, _D, _D, _D]),
+    ("lbm_moments_device", _ST, [_P, _P, _P, _P, _P]),
+    ("lbm_reduce", _ST, [_P, _D]),
+    ("lbm_step_count", ctypes.c_longlong, [_P]),
+    ("lbm_footprint_bytes", ctypes.c_size_t, [ctypes.POINTER(lbm_params)]),
+    ("lbm_checkpoint", _ST, [_P, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    ("lbm_restore", _ST, [_P, _P, ctypes.c_size_t]),
+    ("lbm_free", _ST, [_P]),
+    ("lbm_last_error", ctypes.c_char_p, []),
+    ("lbm_launch_info", _ST, [_P, ctypes.POINTER(ctypes.c_int)]),
+    ("lbm_lattice_info", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D, _D, _D]),
+    ("lbm_coexistence", _ST, [ctypes.c_double, _D, _D]),
+    ("lbm_pool_create", _ST, [ctypes.c_size_t, ctypes.c_int, ctypes.c_int, _P, ctypes.POINTER(_P)]),
+    ("lbm_pool_submit", _ST, [_P, ctypes.POINTER(lbm_params), _D, _D, _D, ctypes.c_longlong,
+                              ctypes.POINTER(ctypes.c_longlong)]),
+    ("lbm_pool_run", _ST, [_P]),
+    ("lbm_pool_poll", _ST, [_P, ctypes.c_longlong, ctypes.POINTER(ctypes.c_int),
+                            ctypes.POINTER(ctypes.c_int)]),
+    ("lbm_pool_collect", _ST, [_P, ctypes.c_longlong, _D, _D, _D, _D]),
+    ("lbm_pool_stats", _ST, [_P, ctypes.POINTER(ctypes.c_longlong)]),
+    ("lbm_pool_destroy", _ST, [_P]),
+]
+
+
+def library_path():
+    return _build.LIB
+
+
+def lib():
+    """The loaded HIP library (raises LbmUnavailable if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB):
+            raise LbmUnavailable("HIP library %s is not built; run paper_1705_10045_amd/build.py"
+                                 % _build.LIB)
+        L = ctypes.CDLL(_build.LIB)
+        for name, res, args in _SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(status):
+    if status != LBM_OK:
+        raise LbmError(status, lib().lbm_last_error().decode())
+    return status
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != tuple(shape):
+        raise ValueError("expected shape %s, got %s" % (tuple(shape), a.shape))
+    return a
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(_D)
+
+
+def make_params(Q, shape, physics, storage_bytes=4):
+    nz, ny, nx = shape
+    p = lbm_params(lattice=Q, nx=nx, ny=ny, nz=nz, storage_bytes=storage_bytes)
+    for k in ("tau", "tau_E", "A", "rho_c", "T_c", "p_c", "c_v", "chi", "rhoQ", "T0_baro"):
+        setattr(p, k, float(physics[k]))
+    p.flags = int(physics["flags"])
+    return p
+
+
+# ------------------------------------------------------------------------------------------
+# Entry points (same names as the C ABI)
+# ------------------------------------------------------------------------------------------
+def lbm_init(params, rho0, u0, T0, stream=None):
+    shape = (params.nz, params.ny, params.nx)
+    rho0 = _f64(rho0, shape)
+    u0 = _f64(u0, (3,) + shape)
+    T0 = _f64(T0, shape)
+    h = _P()
+    _check(lib().lbm_init(ctypes.byref(params), _dp(rho0), _dp(u0), _dp(T0),
+                          _P(stream) if stream else None, ctypes.byref(h)))
+    return h
+
+
+def lbm_step(h, nsteps):
+    return _check(lib().lbm_step(h, int(nsteps)))
+
+
+def lbm_step_async(h, nsteps):
+    return _check(lib().lbm_step_async(h, int(nsteps)))
+
+
+def lbm_check(h):
+    return _check(lib().lbm_check(h))
+
+
+def lbm_moments(h, shape):
+    rho = np.empty(shape)
+    us = np.empty((3,) + tuple(shape))
+    E = np.empty(shape)
+    T = np.empty(shape)
+    _check(lib().lbm_moments(h, _dp(rho), _dp(us), _dp(E), _dp(T)))
+    return {"rho": rho, "u_star": us, "E": E, "T": T}
+
+
+def lbm_moments_device(h, rho_ptr, us_ptr, E_ptr, T_ptr):
+    return _check(lib().lbm_moments_device(h, rho_ptr, us_ptr, E_ptr, T_ptr))
+
+
+def lbm_reduce(h):
+    out = np.zeros(5)
+    _check(lib().lbm_reduce(h, _dp(out)))
+    return out
+
+
+def lbm_step_count(h):
+    return lib().lbm_step_count(h)
+
+
+def lbm_footprint_bytes(params):
+    return lib().lbm_footprint_bytes(ctypes.byref(params))
+
+
+def lbm_checkpoint(h):
+    used = ctypes.c_size_t()
+    _check(lib().lbm_checkpoint(h, None, 0, ctypes.byref(used)))
+    buf = ctypes.create_string_buffer(used.value)
+    _check(lib().lbm_checkpoint(h, buf, used.value, ctypes.byref(used)))
+    return buf.raw
+
+
+def lbm_restore(h, data):
+    buf = ctypes.create_string_buffer(data, len(data))
+    return _check(lib().lbm_restore(h, buf, len(data)))
+
+
+def lbm_free(h):
+    return _check(lib().lbm_free(h))
+
+
+def lbm_last_error():
+    return lib().lbm_last_error().decode()
+
+
+def lbm_launch_info(h):
+    info = (ctypes.c_int * 4)()
+    _check(lib().lbm_launch_info(h, info))
+    return {"tile_x": info[0], "tile_y": info[1], "chunk": info[2], "workgroups": info[3]}
+
+
+def lbm_lattice_info(Q):
+    c = (ctypes.c_int * (3 * Q))()
+    w = np.zeros(Q)
+    G = np.zeros(Q)
+    alpha = ctypes.c_double()
+    D = lib().lbm_lattice_info(Q, c, _dp(w), _dp(G), ctypes.byref(alpha))
+    if D < 0:
+        raise LbmError(D, "unsupported lattice")
+    return np.array(list(c)).reshape(Q, 3), w, G, alpha.value, D
+
+
+def lbm_coexistence(Tr):
+    rv, rl = ctypes.c_double(), ctypes.c_double()
+    _check(lib().lbm_coexistence(float(Tr), ctypes.byref(rv), ctypes.byref(rl)))
+    return rv.value, rl.value
+
+
+# ------------------------------------------------------------------------------------------
+# Convenience wrapper
+# ------------------------------------------------------------------------------------------
+class Sim:
+    """One simulation on the current HIP device (owns its lbm_sim handle)."""
+
+    def __init__(self, Q, physics, rho0, u0, T0, storage_bytes=4, stream=None):
+        rho0 = np.asarray(rho0)
+        self.shape = tuple(rho0.shape)
+        self.Q = Q
+        self.params = make_params(Q, self.shape, physics, storage_bytes)
+        self._h = lbm_init(self.params, rho0, u0, T0, stream)
+
+    def step(self, n=1):
+        lbm_step(self._h, n)
+
+    def step_async(self, n=1):
+        lbm_step_async(self._h, n)
+
+    def check(self):
+        lbm_check(self._h)
+
+    def moments(self):
+        return lbm_moments(self._h, self.shape)
+
+    def reduce(self):
+        return lbm_reduce(self._h)
+
+    def checkpoint(self):
+        return lbm_checkpoint(self._h)
+
+    def restore(self, data):
+        lbm_restore(self._h, data)
+
+    def launch_info(self):
+        return lbm_launch_info(self._h)
+
+    @property
+    def step_count(self):
+        return lbm_step_count(self._h)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lbm_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

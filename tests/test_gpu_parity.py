@@ -1,0 +1,176 @@
+"""GPU parity: the HIP library against the FP64 oracle, element by element, on the same seeded
+inputs.  Sizes span several workgroup tiles (32 x 8 or 32 x 4 nodes, z chunks) with ragged
+tails in every direction.
+
+Tolerances (relative max-norm per field; velocities relative to max(|u*|, 0.01)):
+  FP32 storage: 1e-5 after 100 steps (FP32 arithmetic with FP64 EOS and latent band);
+  FP64 storage: 1e-11 after 100 steps (same FP64 arithmetic as the oracle, other summation
+  order and fused multiply-adds, amplified by the dynamics)."""
+import numpy as np
+import pytest
+
+from paper_1705_10045_amd import inputs as I
+from paper_1705_10045_amd import lbm
+from parity import compare, describe, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = {4: 1e-5, 8: 1e-11}
+
+
+def droplet(shape=(28, 36, 40), radius=8.0, **phys):
+    return I.droplet_3d(shape=shape, radius=radius, params=I.physics(**phys))
+
+
+def spinodal(shape=(30, 34, 36), **phys):
+    return I.spinodal_3d(shape=shape, params=I.physics(**phys))
+
+
+@pytest.mark.parametrize("storage", [4, 8])
+def test_d3q19_moving_droplet_100_steps(storage):
+    errs, g, o, gt, ot = compare(droplet(), 100, storage)
+    describe("D3Q19 droplet %dB" % storage, errs)
+    assert max(errs.values()) < TOL[storage]
+
+
+@pytest.mark.parametrize("storage", [4, 8])
+def test_d2q9_slab_full_size_100_steps(storage):
+    """The 128 x 128 D2Q9 slab workload (width 40, T~ = 0.85, +-1% noise) itself."""
+    case = I.slab_2d()
+    errs, *_ = compare(case, 100, storage)
+    describe("D2Q9 slab 128^2 %dB" % storage, errs)
+    assert max(errs.values()) < TOL[storage]
+
+
+def test_d3q19_spinodal_fp64_100_steps():
+    errs, *_ = compare(spinodal(), 100, 8)
+    describe("D3Q19 spinodal 8B", errs)
+    assert max(errs.values()) < 1e-11
+
+
+def test_d3q19_spinodal_fp32_against_chaos_floor():
+    """Spinodal decomposition amplifies rounding exponentially.  The FP32 error is reported next
+    to the 'chaos floor': the difference the oracle itself shows after perturbing its FP64 input
+    density by one part in 1e7 (FP32 rounding of the state).  The GPU error must stay within a
+    small multiple of that floor."""
+    case = spinodal()
+    errs, g, o, *_ = compare(case, 100, 4)
+    pert = dict(case)
+    pert["rho0"] = case["rho0"] * (1.0 + 6e-8 * I.symmetric(99, case["rho0"].size)
+                                   .reshape(case["rho0"].shape))
+    p, _ = run_oracle(pert, 100)
+    floor = {k: float(np.abs(p[k] - o[k]).max() / max(np.abs(o[k]).max(), 0.01 if k == "u_star" else 0))
+             for k in ("rho", "u_star", "E", "T")}
+    describe("D3Q19 spinodal 4B", errs)
+    describe("   chaos floor", floor)
+    for k in errs:
+        assert errs[k] < max(1e-5, 20 * floor[k])
+
+
+FLAG_SETS = [0, I.WORK, I.CONDUCTION, I.PSEUDOFORCE, I.WORK | I.LATENT | I.PSEUDOFORCE,
+             I.BAROTROPIC | I.PSEUDOFORCE | I.CONDUCTION, I.ALL_TERMS]
+
+
+@pytest.mark.parametrize("flags", FLAG_SETS)
+def test_each_physical_term_fp64(flags):
+    case = droplet(shape=(14, 19, 37), radius=5.0, flags=flags, T0_baro=0.8, rhoQ=0.01 * I.P_C * 50)
+    errs, *_ = compare(case, 30, 8)
+    describe("flags %d" % flags, errs)
+    assert max(errs.values()) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 3, 5), (7, 5, 3), (64, 1, 1), (1, 64, 1),
+                                   (1, 1, 64), (3, 9, 70), (33, 2, 2)])
+def test_edge_shapes_fp64(shape):
+    """Degenerate and ragged boxes: single node, quasi-1D along each axis, fewer planes than a
+    z chunk, extents below the tile size."""
+    rv, rl = I.coexistence(0.8)
+    n = int(np.prod(shape))
+    rho = (0.5 * (rv + rl) * (1 + 0.05 * I.symmetric(5, n))).reshape(shape)
+    case = dict(Q=19, params=I.physics(), rho0=rho,
+                u0=0.02 * I.symmetric(6, 3 * n).reshape((3,) + shape),
+                T0=np.full(shape, 0.8))
+    errs, *_ = compare(case, 20, 8)
+    describe("shape %s" % (shape,), errs)
+    assert max(errs.values()) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 97), (1, 97, 1), (1, 13, 70)])
+def test_edge_shapes_d2q9_fp64(shape):
+    n = int(np.prod(shape))
+    rho = (0.9 * (1 + 0.05 * I.symmetric(7, n))).reshape(shape)
+    case = dict(Q=9, params=I.physics(), rho0=rho,
+                u0=0.02 * I.symmetric(8, 3 * n).reshape((3,) + shape) * np.array([1, 1, 0])[:, None, None, None],
+                T0=np.full(shape, 0.85))
+    errs, *_ = compare(case, 25, 8)
+    describe("d2q9 shape %s" % (shape,), errs)
+    assert max(errs.values()) < 1e-12
+
+
+@pytest.mark.parametrize("storage", [4, 8])
+def test_initial_state(storage):
+    """Step 0: the stored equilibrium reproduces rho0, u*, E0 = rho0 c_v T0 and T0."""
+    case = droplet(shape=(9, 10, 11), radius=3.0)
+    errs, g, o, gt, ot = compare(case, 0, storage)
+    describe("initial %dB" % storage, errs)
+    assert max(errs.values()) < (2e-7 if storage == 4 else 1e-15)
+    assert np.allclose(gt, ot, rtol=1e-6 if storage == 4 else 1e-13, atol=1e-9)
+
+
+@pytest.mark.parametrize("storage", [4, 8])
+def test_reductions_and_conservation(storage):
+    case = droplet(shape=(20, 24, 40), radius=6.0)
+    with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"],
+                 storage_bytes=storage) as s:
+        t0 = s.reduce()
+        s.step(150)
+        t1 = s.reduce()
+    _, ot0 = run_oracle(case, 0)
+    _, ot1 = run_oracle(case, 150)
+    tol = 1e-7 if storage == 4 else 1e-13
+    assert t0 == pytest.approx(ot0, rel=tol, abs=1e-9)
+    assert t1 == pytest.approx(ot1, rel=100 * tol, abs=1e-7 if storage == 4 else 1e-11)
+    # mass and momentum conserved on the device itself
+    assert t1[0] == pytest.approx(t0[0], rel=1e-9 if storage == 4 else 1e-14)
+    assert np.allclose(t1[1:4], t0[1:4], atol=(1e-9 if storage == 4 else 1e-14) * t0[0])
+
+
+def test_energy_conserved_without_work_and_latent():
+    case = droplet(shape=(16, 20, 24), radius=5.0, flags=I.CONDUCTION | I.PSEUDOFORCE)
+    for storage, tol in ((8, 1e-14), (4, 1e-8)):
+        with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"],
+                     storage_bytes=storage) as s:
+            e0 = s.reduce()[4]
+            s.step(100)
+            assert s.reduce()[4] == pytest.approx(e0, rel=tol)
+
+
+def test_checkpoint_restore_and_determinism():
+    case = droplet(shape=(12, 16, 20), radius=4.0)
+    with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"]) as s:
+        s.step(30)
+        ck = s.checkpoint()
+        s.step(30)
+        a = s.moments()
+        s.restore(ck)
+        assert s.step_count == 30
+        s.step(30)
+        b = s.moments()
+    for k in a:
+        assert np.array_equal(a[k], b[k])
+    g2, _ = run_gpu(case, 60, 4)
+    for k in a:
+        assert np.array_equal(a[k], g2[k])
+
+
+def test_unstable_state_reported():
+    """A voxel-sharp dense drop (valid initial field) with a near-1/2 relaxation time leaves the
+    EOS domain within a step (the oracle does too); the step reports LBM_EUNSTABLE (kernels
+    finish normally and flag the node)."""
+    shape = (12, 12, 12)
+    rho = I.two_phase(I.sphere_mask(shape, 3), 2.3, 0.02)
+    p = I.physics(tau=0.501)
+    with lbm.Sim(19, p, rho, I.uniform_velocity(shape, (0.3, 0, 0)), np.full(shape, 0.6)) as s:
+        with pytest.raises(lbm.LbmError) as e:
+            s.step(200)
+        assert e.value.status == lbm.LBM_EUNSTABLE
