@@ -271,6 +271,10 @@ lbm_status upload_table(lbm_sim* s)
 
 lbm_status enqueue_steps(lbm_sim* s, int nsteps)
 {
+    if (!s->aux.err || !s->aux.maxwell || !s->buf[0] || !s->buf[1]) {
+        set_error("simulation is not fully initialised (null device pointer)");
+        return LBM_EDEVICE;
+    }
     for (int i = 0; i < nsteps; ++i) {
         hipError_t e = launch_step(s->p.lattice, s->p.storage_bytes, s->buf[s->cur], s->buf[1 - s->cur],
                                    s->geom, s->phys, s->aux, s->stream);
@@ -374,6 +378,7 @@ lbm_status lbm_init(const lbm_params* params, const double* rho0, const double* 
     s->red_blocks = reduce_blocks(s->n);
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_partials, sizeof(double) * (5 * s->red_blocks + 8));
     if (e != hipSuccess) { lbm_status r = hip_fail(e, "hipMalloc(state)"); lbm_free(s); return r; }
+    s->aux.err = s->d_err;
     hipMemsetAsync(s->d_err, 0, sizeof(int) * 16, s->stream);
     // zero padding so checkpoints are deterministic
     hipMemsetAsync(s->buf[0], 0, bytes, s->stream);

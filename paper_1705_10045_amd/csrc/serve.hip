@@ -1,29 +1,469 @@
-// Serving pool (include/lbm_mi355x.h, lbm_pool_*).
+// Serving pool (include/lbm_mi355x.h, lbm_pool_*): many independent D3Q19 FP32 simulations
+// resident in one HBM arena and advanced together.
+//
+// Device side: a slot table (one SlotDesc per slot) and a flat work list of tiles: slot s owns
+// the global tile indices [tile_begin, tile_begin + ntiles).  One step of every active slot is
+// ONE launch of k_pool_step over a fixed grid that walks the work list, followed by
+// k_pool_advance, which flips each slot's buffer parity, counts its steps down and retires it
+// when done or when its error word is set.  steps_per_run such pairs are captured once into a
+// HIP graph; admissions and collections only rewrite the slot table between replays, so the
+// graph is never re-captured.
+//
+// Host side: first-fit allocation of slot buffers inside one arena allocated at creation
+// (admission by footprint never calls the allocator of the runtime), tickets, and the
+// completion bookkeeping read back after each replay.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <vector>
+
 #include "../../include/lbm_mi355x.h"
+#include "kernels.hpp"
 #include "sim.hpp"
+#include "step_kernel.hpp"
+
+namespace lbm {
+
+constexpr int kPoolTX = 32, kPoolTY = 8;   // tile of the FP32 D3Q19 step
+constexpr int kPoolChunk = 8;              // z planes per tile: uniform tile work in the mix
+constexpr int kPoolGrid = 2048;            // workgroups of the persistent batched launch
+constexpr int kPoolMaxEdge = 128;
+
+struct SlotDesc {
+    float* buf[2];
+    StepGeom geom;
+    Phys phys;
+    int tile_begin;
+    int ntiles;
+    int parity;        // buf[parity] holds the current state
+    int active;        // 1 while steps remain and no error was flagged
+    long long remaining;
+    long long steps_done;
+};
+
+struct PoolHeader {
+    int nslots;        // slots [0, nslots) are searched by the step kernel
+    int total_tiles;
+};
+
+__global__ void __launch_bounds__(kPoolTX* kPoolTY)
+k_pool_step(const SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ hdr,
+            const double* __restrict__ table, double s0, double inv_ds, int* __restrict__ errs)
+{
+    const int total = hdr->total_tiles;
+    const int nslots = hdr->nslots;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        // slot owning tile t: last slot with tile_begin <= t (binary search, workgroup-uniform)
+        int lo = 0, hi = nslots - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (slots[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+        }
+        const SlotDesc& d = slots[lo];
+        if (!d.active || t - d.tile_begin >= d.ntiles) continue;
+        // workgroup-uniform copies, so the stores of the step cannot alias them
+        const StepGeom g = d.geom;
+        const Phys ph = d.phys;
+        const int parity = d.parity;
+        const int local = t - d.tile_begin;
+        const float* src = d.buf[parity];
+        float* dst = d.buf[1 - parity];
+        StepAux aux;
+        aux.maxwell = table;
+        aux.tab_s0 = s0;
+        aux.tab_inv_ds = inv_ds;
+        aux.err = errs + lo;
+        step_tile<19, float, float, kPoolTX, kPoolTY>(src, dst, g, ph, aux, local);
+    }
+}
+
+__global__ void k_pool_advance(SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ hdr,
+                               const int* __restrict__ errs)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= hdr->nslots) return;
+    SlotDesc& d = slots[s];
+    if (!d.active) return;
+    d.parity ^= 1;
+    d.steps_done += 1;
+    d.remaining -= 1;
+    if (d.remaining <= 0 || errs[s] != 0) d.active = 0;
+}
+
+}  // namespace lbm
 
 using namespace lbm;
 
+struct PoolSlot {
+    bool used = false;
+    long long ticket = -1;
+    size_t offset = 0, bytes = 0;
+    lbm_params params;
+    long long nsteps = 0;
+};
+
+struct lbm_pool {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t budget = 0, in_use = 0;
+    char* arena = nullptr;
+    std::map<size_t, size_t> free_blocks;   // offset -> size, coalesced
+    int max_slots = 0, steps_per_run = 1;
+    std::vector<PoolSlot> slots;
+    std::vector<SlotDesc> table;             // host mirror of the device slot table
+    SlotDesc* d_slots = nullptr;
+    PoolHeader* d_hdr = nullptr;
+    int* d_errs = nullptr;
+    double* d_table = nullptr;
+    double tab_s0 = 0, tab_inv_ds = 0;
+    double* d_staging = nullptr;             // initial fields of a request (5 n doubles)
+    double* d_scratch = nullptr;             // moment scratch (10 n doubles)
+    PoolHeader hdr{0, 0};                    // host copy of the device header (persistent for async copies)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool dirty = true;
+    long long next_ticket = 1;
+    std::map<long long, int> ticket_slot;
+    std::map<long long, lbm_status> finished;  // collected-or-not results by ticket
+};
+
+namespace {
+
+const size_t kAlign = 256;
+
+bool arena_alloc(lbm_pool* p, size_t bytes, size_t& off)
+{
+    bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+    for (auto it = p->free_blocks.begin(); it != p->free_blocks.end(); ++it) {
+        if (it->second >= bytes) {
+            off = it->first;
+            const size_t rest = it->second - bytes;
+            p->free_blocks.erase(it);
+            if (rest) p->free_blocks[off + bytes] = rest;
+            p->in_use += bytes;
+            return true;
+        }
+    }
+    return false;
+}
+
+void arena_free(lbm_pool* p, size_t off, size_t bytes)
+{
+    bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+    p->in_use -= bytes;
+    auto it = p->free_blocks.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != p->free_blocks.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        p->free_blocks.erase(nx);
+    }
+    if (it != p->free_blocks.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            p->free_blocks.erase(it);
+        }
+    }
+}
+
+StepGeom pool_geometry(const lbm_params& p)
+{
+    StepGeom g;
+    g.nx = p.nx; g.ny = p.ny; g.nz = p.nz;
+    g.plane = padded_plane((long long)p.nx * p.ny * p.nz);
+    g.ntx = (p.nx + kPoolTX - 1) / kPoolTX;
+    g.nty = (p.ny + kPoolTY - 1) / kPoolTY;
+    g.chunk = kPoolChunk < p.nz ? kPoolChunk : p.nz;
+    g.nchunks = (p.nz + g.chunk - 1) / g.chunk;
+    return g;
+}
+
+// Rebuild the work list (tile prefix over slots in index order) and upload the table.
+lbm_status upload_table(lbm_pool* p)
+{
+    int total = 0, nslots = 0;
+    for (int s = 0; s < p->max_slots; ++s) {
+        SlotDesc& d = p->table[s];
+        d.tile_begin = total;
+        if (p->slots[s].used && d.active) {
+            d.ntiles = d.geom.ntx * d.geom.nty * d.geom.nchunks;
+            total += d.ntiles;
+            nslots = s + 1;
+        } else {
+            d.ntiles = 0;
+        }
+    }
+    p->hdr.nslots = nslots;
+    p->hdr.total_tiles = total;
+    hipError_t e = hipMemcpyAsync(p->d_slots, p->table.data(), sizeof(SlotDesc) * p->max_slots,
+                                  hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->d_hdr, &p->hdr, sizeof(PoolHeader), hipMemcpyHostToDevice, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "pool table upload");
+    p->dirty = false;
+    return LBM_OK;
+}
+
+lbm_status capture_graph(lbm_pool* p)
+{
+    hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "graph capture begin");
+    const int adv_blocks = (p->max_slots + 255) / 256;
+    for (int i = 0; i < p->steps_per_run; ++i) {
+        hipLaunchKernelGGL(k_pool_step, dim3(kPoolGrid), dim3(kPoolTX * kPoolTY), 0, p->stream,
+                           p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
+        hipLaunchKernelGGL(k_pool_advance, dim3(adv_blocks), dim3(256), 0, p->stream, p->d_slots,
+                           p->d_hdr, p->d_errs);
+    }
+    e = hipStreamEndCapture(p->stream, &p->graph);
+    if (e != hipSuccess) return hip_fail(e, "graph capture end");
+    e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    return LBM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
-lbm_status lbm_pool_create(size_t, int, int, void*, lbm_pool** out)
+lbm_status lbm_pool_create(size_t hbm_budget_bytes, int max_slots, int steps_per_run, void* stream,
+                           lbm_pool** out)
 {
-    if (out) *out = nullptr;
-    set_error("serving pool not available in this build");
-    return LBM_EINVAL;
+    clear_error();
+    if (!out) { set_error("out is NULL"); return LBM_EINVAL; }
+    *out = nullptr;
+    if (max_slots < 1 || max_slots > 4096 || steps_per_run < 1 || steps_per_run > 1000 ||
+        hbm_budget_bytes < ((size_t)1 << 20)) {
+        set_error("pool needs 1 <= max_slots <= 4096, 1 <= steps_per_run <= 1000, budget >= 1 MiB");
+        return LBM_EINVAL;
+    }
+    double rv, rl;
+    if (!host_band_limits(0.8, rv, rl)) { set_error("Maxwell table unavailable"); return LBM_EDEVICE; }
+    lbm_pool* p = new lbm_pool();
+    hipGetDevice(&p->device);
+    if (stream) {
+        p->stream = (hipStream_t)stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { delete p; return hip_fail(e, "hipStreamCreate"); }
+        p->own_stream = true;
+    }
+    p->budget = hbm_budget_bytes / kAlign * kAlign;
+    p->max_slots = max_slots;
+    p->steps_per_run = steps_per_run;
+    p->slots.assign(max_slots, PoolSlot());
+    p->table.assign(max_slots, SlotDesc());
+    memset(p->table.data(), 0, sizeof(SlotDesc) * max_slots);
+    const long long nmax = (long long)kPoolMaxEdge * kPoolMaxEdge * kPoolMaxEdge;
+    hipError_t e = hipMalloc((void**)&p->arena, p->budget);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_slots, sizeof(SlotDesc) * max_slots);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_hdr, sizeof(PoolHeader));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_errs, sizeof(int) * max_slots);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_staging, sizeof(double) * 5 * nmax);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_scratch, sizeof(double) * 10 * nmax);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_table, sizeof(double) * 2 * kMaxwellPoints);
+    if (e != hipSuccess) { lbm_status r = hip_fail(e, "pool allocation"); lbm_pool_destroy(p); return r; }
+    p->free_blocks[0] = p->budget;
+    // table of the band limits, the same one every simulation uses
+    std::vector<double> tab(2 * kMaxwellPoints);
+    const double s_lo = std::sqrt(1.0 - kLatentTmax), s_hi = std::sqrt(1.0 - kLatentTmin);
+    const double ds = (s_hi - s_lo) / (kMaxwellPoints - 1);
+    for (int i = 0; i < kMaxwellPoints; ++i) {
+        const double Tr = 1.0 - (s_lo + i * ds) * (s_lo + i * ds);
+        host_band_limits(Tr < kLatentTmin ? kLatentTmin : Tr, tab[2 * i], tab[2 * i + 1]);
+    }
+    p->tab_s0 = s_lo;
+    p->tab_inv_ds = 1.0 / ds;
+    e = hipMemcpyAsync(p->d_table, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(p->d_errs, 0, sizeof(int) * max_slots, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) { lbm_status r = hip_fail(e, "pool setup"); lbm_pool_destroy(p); return r; }
+    lbm_status st = upload_table(p);
+    if (st == LBM_OK) st = capture_graph(p);
+    if (st != LBM_OK) { lbm_pool_destroy(p); return st; }
+    *out = p;
+    return LBM_OK;
 }
-lbm_status lbm_pool_submit(lbm_pool*, const lbm_params*, const double*, const double*, const double*,
-                           long long, long long*)
+
+lbm_status lbm_pool_submit(lbm_pool* p, const lbm_params* params, const double* rho0, const double* u0,
+                           const double* T0, long long nsteps, long long* ticket)
 {
-    set_error("serving pool not available in this build");
-    return LBM_EINVAL;
+    clear_error();
+    if (!p || !ticket || nsteps < 1) { set_error("bad pool, ticket pointer or step count"); return LBM_EINVAL; }
+    lbm_status st = validate_params(params);
+    if (st != LBM_OK) return st;
+    if (params->lattice != 19 || params->storage_bytes != 4 || params->nx > kPoolMaxEdge ||
+        params->ny > kPoolMaxEdge || params->nz > kPoolMaxEdge) {
+        set_error("pool requests must be D3Q19, FP32 storage, edges <= %d", kPoolMaxEdge);
+        return LBM_EINVAL;
+    }
+    st = validate_fields(*params, rho0, u0, T0);
+    if (st != LBM_OK) return st;
+    int slot = -1;
+    for (int s = 0; s < p->max_slots; ++s)
+        if (!p->slots[s].used) { slot = s; break; }
+    if (slot < 0) { set_error("no free slot"); return LBM_EBUSY; }
+    const size_t half = state_bytes(*params);
+    const size_t half_al = (half + kAlign - 1) / kAlign * kAlign;
+    size_t off = 0;
+    if (!arena_alloc(p, 2 * half_al, off)) {
+        set_error("request needs %zu bytes; %zu of %zu in use", 2 * half_al, p->in_use, p->budget);
+        return LBM_EBUSY;
+    }
+    hipSetDevice(p->device);
+    PoolSlot& ps = p->slots[slot];
+    ps.used = true;
+    ps.offset = off;
+    ps.bytes = 2 * half_al;
+    ps.params = *params;
+    ps.nsteps = nsteps;
+    ps.ticket = p->next_ticket++;
+    SlotDesc& d = p->table[slot];
+    memset(&d, 0, sizeof(d));
+    d.buf[0] = (float*)(p->arena + off);
+    d.buf[1] = (float*)(p->arena + off + half_al);
+    d.geom = pool_geometry(*params);
+    d.phys = make_phys(*params);
+    d.parity = 0;
+    d.active = 1;
+    d.remaining = nsteps;
+    const long long n = (long long)params->nx * params->ny * params->nz;
+    hipError_t e = hipMemsetAsync(p->arena + off, 0, 2 * half_al, p->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(p->d_errs + slot, 0, sizeof(int), p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->d_staging, rho0, sizeof(double) * n, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->d_staging + n, u0, sizeof(double) * 3 * n, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->d_staging + 4 * n, T0, sizeof(double) * n, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess)
+        e = launch_init(19, 4, d.buf[0], p->d_staging, p->d_staging + n, p->d_staging + 4 * n, params->nx,
+                        params->ny, params->nz, d.geom.plane, params->c_v, p->stream);
+    // the staging buffer is reused by the next submission: wait for this upload
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) {
+        arena_free(p, off, 2 * half_al);
+        ps = PoolSlot();
+        return hip_fail(e, "request upload");
+    }
+    p->ticket_slot[ps.ticket] = slot;
+    p->dirty = true;
+    *ticket = ps.ticket;
+    return LBM_OK;
 }
-lbm_status lbm_pool_run(lbm_pool*) { set_error("serving pool not available"); return LBM_EINVAL; }
-lbm_status lbm_pool_poll(lbm_pool*, long long, int*, lbm_status*) { set_error("serving pool not available"); return LBM_EINVAL; }
-lbm_status lbm_pool_collect(lbm_pool*, long long, double*, double*, double*, double*) { set_error("serving pool not available"); return LBM_EINVAL; }
-lbm_status lbm_pool_stats(const lbm_pool*, long long*) { set_error("serving pool not available"); return LBM_EINVAL; }
-lbm_status lbm_pool_destroy(lbm_pool*) { return LBM_OK; }
+
+lbm_status lbm_pool_run(lbm_pool* p)
+{
+    clear_error();
+    if (!p) { set_error("pool is NULL"); return LBM_EINVAL; }
+    hipSetDevice(p->device);
+    if (p->dirty) {
+        lbm_status st = upload_table(p);
+        if (st != LBM_OK) return st;
+    }
+    bool any = false;
+    for (int s = 0; s < p->max_slots; ++s) any = any || (p->slots[s].used && p->table[s].active);
+    if (!any) return LBM_OK;
+    hipError_t e = hipGraphLaunch(p->exec, p->stream);
+    std::vector<int> errs(p->max_slots);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->table.data(), p->d_slots, sizeof(SlotDesc) * p->max_slots, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(errs.data(), p->d_errs, sizeof(int) * p->max_slots, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "pool replay");
+    for (int s = 0; s < p->max_slots; ++s) {
+        PoolSlot& ps = p->slots[s];
+        if (!ps.used || p->finished.count(ps.ticket)) continue;
+        if (errs[s]) p->finished[ps.ticket] = LBM_EUNSTABLE;
+        else if (!p->table[s].active) p->finished[ps.ticket] = LBM_OK;
+    }
+    // slots that finished no longer contribute tiles: rebuild the work list before the next replay
+    for (int s = 0; s < p->max_slots; ++s)
+        if (p->slots[s].used && !p->table[s].active) { p->dirty = true; break; }
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_poll(lbm_pool* p, long long ticket, int* done, lbm_status* result)
+{
+    clear_error();
+    if (!p || !done) { set_error("NULL argument"); return LBM_EINVAL; }
+    auto it = p->ticket_slot.find(ticket);
+    if (it == p->ticket_slot.end()) { set_error("unknown ticket %lld", ticket); return LBM_EINVAL; }
+    auto f = p->finished.find(ticket);
+    *done = f != p->finished.end();
+    if (result) *result = *done ? f->second : LBM_OK;
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_collect(lbm_pool* p, long long ticket, double* rho, double* u_star, double* E, double* T)
+{
+    clear_error();
+    if (!p) { set_error("pool is NULL"); return LBM_EINVAL; }
+    auto it = p->ticket_slot.find(ticket);
+    if (it == p->ticket_slot.end()) { set_error("unknown ticket %lld", ticket); return LBM_EINVAL; }
+    auto f = p->finished.find(ticket);
+    if (f == p->finished.end()) { set_error("ticket %lld has not finished", ticket); return LBM_EBUSY; }
+    const int s = it->second;
+    PoolSlot& ps = p->slots[s];
+    const SlotDesc& d = p->table[s];
+    hipSetDevice(p->device);
+    const long long n = (long long)ps.params.nx * ps.params.ny * ps.params.nz;
+    double* scr = p->d_scratch;
+    double* d_us = scr + 7 * n;
+    int* d_err = p->d_errs + s;
+    hipError_t e = launch_moments(19, 4, d.buf[d.parity], scr, ps.params.nx, ps.params.ny, ps.params.nz,
+                                  d.geom.plane, d.phys, d_err, nullptr, u_star ? d_us : nullptr, nullptr,
+                                  nullptr, p->stream);
+    if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, scr, sizeof(double) * n, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess && u_star) e = hipMemcpyAsync(u_star, d_us, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess && E) e = hipMemcpyAsync(E, scr + 4 * n, sizeof(double) * n, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess && T) e = hipMemcpyAsync(T, scr + 5 * n, sizeof(double) * n, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "collect");
+    const lbm_status result = f->second;
+    arena_free(p, ps.offset, ps.bytes);
+    p->ticket_slot.erase(it);
+    p->finished.erase(f);
+    ps = PoolSlot();
+    memset(&p->table[s], 0, sizeof(SlotDesc));
+    p->dirty = true;
+    if (result != LBM_OK) set_error("request %lld left the EOS domain", ticket);
+    return result;
+}
+
+lbm_status lbm_pool_stats(const lbm_pool* p, long long out[4])
+{
+    if (!p || !out) { set_error("NULL argument"); return LBM_EINVAL; }
+    long long active = 0, free_slots = 0;
+    for (int s = 0; s < p->max_slots; ++s) {
+        if (p->slots[s].used && p->table[s].active) ++active;
+        if (!p->slots[s].used) ++free_slots;
+    }
+    out[0] = active;
+    out[1] = (long long)p->in_use;
+    out[2] = (long long)p->budget;
+    out[3] = free_slots;
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_destroy(lbm_pool* p)
+{
+    if (!p) return LBM_OK;
+    hipSetDevice(p->device);
+    if (p->stream) hipStreamSynchronize(p->stream);
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->arena) hipFree(p->arena);
+    if (p->d_slots) hipFree(p->d_slots);
+    if (p->d_hdr) hipFree(p->d_hdr);
+    if (p->d_errs) hipFree(p->d_errs);
+    if (p->d_staging) hipFree(p->d_staging);
+    if (p->d_scratch) hipFree(p->d_scratch);
+    if (p->d_table) hipFree(p->d_table);
+    if (p->own_stream && p->stream) hipStreamDestroy(p->stream);
+    delete p;
+    return LBM_OK;
+}
 
 }  // extern "C"

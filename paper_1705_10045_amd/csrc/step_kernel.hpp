@@ -70,10 +70,12 @@ __device__ __forceinline__ void region_slot(int s, int& rx, int& ry)
     rx = c < HALO ? c : RW - 2 * HALO + c;
 }
 
+// One workgroup's share of a step: tile `lb` (x fastest, then y, then z chunk) of the box
+// described by g.  Must be called by all TX*TY threads of the workgroup.
 template <int Q, class S, class R, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY)
-k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const Phys ph,
-       const StepAux aux)
+__device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restrict__ dst,
+                                          const StepGeom& g, const Phys& ph, const StepAux& aux,
+                                          const int lb)
 {
     using L = Lattice<Q>;
     constexpr int D = L::D;
@@ -85,15 +87,13 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const P
     constexpr int ME = (NE + NT - 1) / NT;
     constexpr int MF = (NF + NT - 1) / NT;
 
-    __shared__ R sPhi[RING][NE];
+    __shared__ double sPhi[RING][NE];   // Phi in FP64: the force is a small difference of Phi^2
     __shared__ R sRho[RING][NE];
     __shared__ R sT[RING][NE];
     __shared__ R sJ[3][RING][NE];
     __shared__ R sU[3][RING][NF];
 
     const int tid = threadIdx.x;
-    const int nblk = gridDim.x;
-    const int lb = xcd_logical_block(blockIdx.x, nblk);
     const int tix = lb % g.ntx;
     const int tiy = (lb / g.ntx) % g.nty;
     const int tiz = lb / (g.ntx * g.nty);
@@ -146,8 +146,7 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const P
     const int ys[3] = {m_y[0][0], m_y[0][1], m_y[0][2]};
 
     const R omega = R(ph.omega), omega_E = R(ph.omega_E);
-    const R Amix = R(ph.A), inv_alpha = R(ph.inv_alpha);
-    const R c_v = R(ph.c_v), cond_half = R(ph.cond_half);
+    const R cond_half = R(ph.cond_half);
     const unsigned flags = ph.flags;
 
     // register ring of the own node's moments: [0] newest plane ... [ZH] plane being collided
@@ -177,31 +176,33 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const P
 #pragma unroll
         for (int r = 0; r < ME; ++r) {
             if (m_e[r] < 0) continue;
-            R rho = R(0), jx = R(0), jy = R(0), jz = R(0), E = R(0);
+            // moments summed in FP64 (exact for FP32 populations up to the final rounding)
+            double dr = 0.0, djx = 0.0, djy = 0.0, djz = 0.0, dE = 0.0;
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
                 const long long off = (long long)zoff[1 - L::cz[k]] + m_y[r][1 - L::cy[k]] +
                                       m_x[r][1 - L::cx[k]];
-                const R n = R(src[(long long)k * g.plane + off]);
-                const R e = R(src[(long long)(Q + k) * g.plane + off]);
-                rho += n;
-                E += e;
-                if (L::cx[k] == 1) jx += n; else if (L::cx[k] == -1) jx -= n;
-                if (L::cy[k] == 1) jy += n; else if (L::cy[k] == -1) jy -= n;
-                if (L::cz[k] == 1) jz += n; else if (L::cz[k] == -1) jz -= n;
+                const double n = double(src[(long long)k * g.plane + off]);
+                const double e = double(src[(long long)(Q + k) * g.plane + off]);
+                dr += n;
+                dE += e;
+                if (L::cx[k] == 1) djx += n; else if (L::cx[k] == -1) djx -= n;
+                if (L::cy[k] == 1) djy += n; else if (L::cy[k] == -1) djy -= n;
+                if (L::cz[k] == 1) djz += n; else if (L::cz[k] == -1) djz -= n;
             }
-            const R T = E / (rho * c_v);
-            const double Te = (flags & kBaro) ? ph.T0_baro : double(T);
-            const double p = vdw_pressure(double(rho), Te, ph);
-            double phi2 = double(rho) * kTheta - p;
-            const bool ok = phi2 > 0.0 && double(rho) * ph.inv_rho_c < 3.0 && rho > R(0) &&
-                            E == E && E < R(1e30);
+            const double dT = dE / (dr * ph.c_v);
+            const double Te = (flags & kBaro) ? ph.T0_baro : dT;
+            const double p = vdw_pressure(dr, Te, ph);
+            double phi2 = dr * kTheta - p;
+            const bool ok = phi2 > 0.0 && dr * ph.inv_rho_c < 3.0 && dr > 0.0 && dE == dE &&
+                            dE < 1e30;
             if (!ok) {
                 atomicOr(aux.err, 1);
                 phi2 = 0.0;
             }
+            const R rho = R(dr), jx = R(djx), jy = R(djy), jz = R(djz), E = R(dE), T = R(dT);
             const int e = m_e[r];
-            sPhi[sm][e] = R(sqrt(phi2));
+            sPhi[sm][e] = sqrt(phi2);
             sRho[sm][e] = rho;
             sT[sm][e] = T;
             sJ[0][sm][e] = jx;
@@ -230,13 +231,14 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const P
             for (int r = 0; r < MF; ++r) {
                 if (f_f[r] < 0) continue;
                 const int e = f_e[r];
-                R s1x = R(0), s1y = R(0), s1z = R(0), s2x = R(0), s2y = R(0), s2z = R(0);
+                // force of section 3 in FP64
+                double s1x = 0, s1y = 0, s1z = 0, s2x = 0, s2y = 0, s2z = 0;
 #pragma unroll
                 for (int k = 1; k < Q; ++k) {
                     const int sl = L::cz[k] == 0 ? sf : (L::cz[k] == 1 ? sfp : sfm);
-                    const R phk = sPhi[sl][e + L::cx[k] + EX * L::cy[k]];
-                    const R gph = R(force_coef<Q>(k)) * phk;
-                    const R gph2 = gph * phk;
+                    const double phk = sPhi[sl][e + L::cx[k] + EX * L::cy[k]];
+                    const double gph = force_coef<Q>(k) * phk;
+                    const double gph2 = gph * phk;
                     if (L::cx[k] == 1) { s1x += gph2; s2x += gph; }
                     else if (L::cx[k] == -1) { s1x -= gph2; s2x -= gph; }
                     if (L::cy[k] == 1) { s1y += gph2; s2y += gph; }
@@ -244,11 +246,10 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const P
                     if (L::cz[k] == 1) { s1z += gph2; s2z += gph; }
                     else if (L::cz[k] == -1) { s1z -= gph2; s2z -= gph; }
                 }
-                const R phc = sPhi[sf][e];
-                const R b = (R(1) - R(2) * Amix) * phc;
-                const R Fx = (Amix * s1x + b * s2x) * inv_alpha;
-                const R Fy = (Amix * s1y + b * s2y) * inv_alpha;
-                const R Fz = (Amix * s1z + b * s2z) * inv_alpha;
+                const double b = (1.0 - 2.0 * ph.A) * sPhi[sf][e];
+                const R Fx = R((ph.A * s1x + b * s2x) * ph.inv_alpha);
+                const R Fy = R((ph.A * s1y + b * s2y) * ph.inv_alpha);
+                const R Fz = R((ph.A * s1z + b * s2z) * ph.inv_alpha);
                 const R rho = sRho[sf][e];
                 const int f = f_f[r];
                 sU[0][sf][f] = (sJ[0][sf][e] + R(0.5) * Fx) / rho;
@@ -334,6 +335,14 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const P
         }
         __syncthreads();
     }
+}
+
+template <int Q, class S, class R, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY)
+k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const Phys ph,
+       const StepAux aux)
+{
+    step_tile<Q, S, R, TX, TY>(src, dst, g, ph, aux, xcd_logical_block(blockIdx.x, gridDim.x));
 }
 
 }  // namespace lbm
