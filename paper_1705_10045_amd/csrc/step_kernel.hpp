@@ -150,13 +150,13 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     const unsigned flags = ph.flags;
 
     // register ring of the own node's moments: [0] newest plane ... [ZH] plane being collided
-    R o_rho[ZH + 1], o_jx[ZH + 1], o_jy[ZH + 1], o_jz[ZH + 1], o_E[ZH + 1], o_T[ZH + 1];
-    double o_p[ZH + 1];
+    double o_rho[ZH + 1], o_E[ZH + 1], o_p[ZH + 1];
+    R o_jx[ZH + 1], o_jy[ZH + 1], o_jz[ZH + 1], o_T[ZH + 1];
     R fcur[3] = {R(0), R(0), R(0)}, fprev[3] = {R(0), R(0), R(0)};
 #pragma unroll
     for (int q = 0; q <= ZH; ++q) {
-        o_rho[q] = R(1); o_jx[q] = o_jy[q] = o_jz[q] = R(0);
-        o_E[q] = R(1); o_T[q] = R(1); o_p[q] = 0.0;
+        o_rho[q] = 1.0; o_jx[q] = o_jy[q] = o_jz[q] = R(0);
+        o_E[q] = 1.0; o_T[q] = R(1); o_p[q] = 0.0;
     }
 
     const int niter = (z1 - z0) + 2 * ZH;
@@ -200,7 +200,7 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
                 atomicOr(aux.err, 1);
                 phi2 = 0.0;
             }
-            const R rho = R(dr), jx = R(djx), jy = R(djy), jz = R(djz), E = R(dE), T = R(dT);
+            const R rho = R(dr), jx = R(djx), jy = R(djy), jz = R(djz), T = R(dT);
             const int e = m_e[r];
             sPhi[sm][e] = sqrt(phi2);
             sRho[sm][e] = rho;
@@ -215,8 +215,8 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
                     o_jz[q] = o_jz[q - 1]; o_E[q] = o_E[q - 1]; o_T[q] = o_T[q - 1];
                     o_p[q] = o_p[q - 1];
                 }
-                o_rho[0] = rho; o_jx[0] = jx; o_jy[0] = jy; o_jz[0] = jz;
-                o_E[0] = E; o_T[0] = T; o_p[0] = p;
+                o_rho[0] = dr; o_jx[0] = jx; o_jy[0] = jy; o_jz[0] = jz;
+                o_E[0] = dE; o_T[0] = T; o_p[0] = p;
             }
         }
         __syncthreads();
@@ -269,7 +269,8 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             const int sc = (zc + 4) & (RING - 1);
             const int scm = (zc + 3) & (RING - 1);
             const int scp = (zc + 5) & (RING - 1);
-            const R rho = o_rho[ZH], E = o_E[ZH], T = o_T[ZH];
+            const double rho_d = o_rho[ZH], E_d = o_E[ZH];
+            const R rho = R(rho_d), E = R(E_d), T = o_T[ZH];
             const double p = o_p[ZH];
             const R* Fo = (ZH > 0) ? fprev : fcur;
             const R ux = o_jx[ZH] / rho, uy = o_jy[ZH] / rho, uz = o_jz[ZH] / rho;
@@ -313,8 +314,14 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             const R vv = vx * vx + vy * vy + vz * vz;
             const R keepN = R(1) - omega, keepG = R(1) - omega_E;
             const bool pseudo = (flags & kPseudo) != 0;
+            // The collision conserves mass and changes the energy by exactly dE (the BGK,
+            // EDM and pseudoforce increments sum to zero; dg(1) sums to dE).  The moving
+            // directions are computed from the equilibria and the rest populations close the
+            // balances in FP64 over the values actually stored, so rounding of the lattice
+            // weights cannot create mass or energy.
+            double sumN = 0.0, sumG = 0.0;
 #pragma unroll
-            for (int k = 0; k < Q; ++k) {
+            for (int k = 1; k < Q; ++k) {
                 const long long off = (long long)(D == 3 ? zpull[1 - L::cz[k]] : zoc) +
                                       ys[1 - L::cy[k]] + xs[1 - L::cx[k]];
                 const R n = R(src[(long long)k * g.plane + off]);
@@ -329,9 +336,14 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
                 // g' = g + (geq(u) - g)/tau_E + g dE/E [+ geq(v) - geq(u)]   (eq:gk, section 4)
                 const R gn = pseudo ? E * Pv + keepG * (e - E * Pu) + e * dEoE
                                     : omega_E * E * Pu + keepG * e + e * dEoE;
-                dst[(long long)k * g.plane + own] = S(nn);
-                dst[(long long)(Q + k) * g.plane + own] = S(gn);
+                const S nn_s = S(nn), gn_s = S(gn);
+                sumN += double(nn_s);
+                sumG += double(gn_s);
+                dst[(long long)k * g.plane + own] = nn_s;
+                dst[(long long)(Q + k) * g.plane + own] = gn_s;
             }
+            dst[own] = S(rho_d - sumN);
+            dst[(long long)Q * g.plane + own] = S(E_d + double(dE) - sumG);
         }
         __syncthreads();
     }

@@ -279,3 +279,108 @@ class Sim:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ------------------------------------------------------------------------------------------
+# Serving pool
+# ------------------------------------------------------------------------------------------
+def lbm_pool_create(hbm_budget_bytes, max_slots, steps_per_run, stream=None):
+    h = _P()
+    _check(lib().lbm_pool_create(int(hbm_budget_bytes), int(max_slots), int(steps_per_run),
+                                 _P(stream) if stream else None, ctypes.byref(h)))
+    return h
+
+
+def lbm_pool_submit(pool, params, rho0, u0, T0, nsteps):
+    """Ticket of the admitted request, or None if the pool is busy (no slot / budget)."""
+    shape = (params.nz, params.ny, params.nx)
+    rho0 = _f64(rho0, shape)
+    u0 = _f64(u0, (3,) + shape)
+    T0 = _f64(T0, shape)
+    t = ctypes.c_longlong()
+    st = lib().lbm_pool_submit(pool, ctypes.byref(params), _dp(rho0), _dp(u0), _dp(T0),
+                               int(nsteps), ctypes.byref(t))
+    if st == LBM_EBUSY:
+        return None
+    _check(st)
+    return t.value
+
+
+def lbm_pool_run(pool):
+    return _check(lib().lbm_pool_run(pool))
+
+
+def lbm_pool_poll(pool, ticket):
+    done = ctypes.c_int()
+    res = ctypes.c_int()
+    _check(lib().lbm_pool_poll(pool, int(ticket), ctypes.byref(done), ctypes.byref(res)))
+    return bool(done.value), res.value
+
+
+def lbm_pool_collect(pool, ticket, shape):
+    """Final fields of a finished request (dict as lbm_moments) and its status."""
+    rho = np.empty(shape)
+    us = np.empty((3,) + tuple(shape))
+    E = np.empty(shape)
+    T = np.empty(shape)
+    st = lib().lbm_pool_collect(pool, int(ticket), _dp(rho), _dp(us), _dp(E), _dp(T))
+    if st not in (LBM_OK, LBM_EUNSTABLE):
+        _check(st)
+    return {"rho": rho, "u_star": us, "E": E, "T": T}, st
+
+
+def lbm_pool_stats(pool):
+    out = (ctypes.c_longlong * 4)()
+    _check(lib().lbm_pool_stats(pool, out))
+    return {"active": out[0], "bytes_in_use": out[1], "budget": out[2], "free_slots": out[3]}
+
+
+def lbm_pool_destroy(pool):
+    return _check(lib().lbm_pool_destroy(pool))
+
+
+class Pool:
+    """Serving pool of D3Q19 FP32 simulations resident on the current device."""
+
+    def __init__(self, hbm_budget_bytes, max_slots=64, steps_per_run=10, stream=None):
+        self._h = lbm_pool_create(hbm_budget_bytes, max_slots, steps_per_run, stream)
+        self.steps_per_run = steps_per_run
+        self._shapes = {}
+
+    def submit(self, physics, rho0, u0, T0, nsteps):
+        rho0 = np.asarray(rho0)
+        params = make_params(19, rho0.shape, physics, 4)
+        t = lbm_pool_submit(self._h, params, rho0, u0, T0, nsteps)
+        if t is not None:
+            self._shapes[t] = tuple(rho0.shape)
+        return t
+
+    def run(self):
+        lbm_pool_run(self._h)
+
+    def poll(self, ticket):
+        return lbm_pool_poll(self._h, ticket)
+
+    def collect(self, ticket):
+        fields, st = lbm_pool_collect(self._h, ticket, self._shapes.pop(ticket))
+        return fields, st
+
+    def stats(self):
+        return lbm_pool_stats(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lbm_pool_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

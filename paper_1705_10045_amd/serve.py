@@ -1,0 +1,148 @@
+"""Continuous-batching serving loop over the device pool (lbm_pool_* in the C ABI).
+
+Requests (independent D3Q19 thermal two-phase simulations of uneven lattice sizes) arrive over
+time.  The loop admits every arrived request that fits a free slot and the remaining HBM
+budget (first fit in arrival order), advances all admitted requests together with one pool
+replay (one batched launch per step, replayed from a HIP graph), collects the finished ones
+and frees their slots for the requests still waiting.  Time-to-result of a request is its
+completion time minus its arrival time.
+
+The scheduler is written against a small executor interface (submit / run / poll / collect /
+stats) so that its bookkeeping can be exercised without a device; `PoolExecutor` is the real
+one, backed by the HIP library.
+"""
+import collections
+import math
+import time
+
+import numpy as np
+
+from . import inputs
+
+
+def poisson_arrivals(count, rate, seed=inputs.SEED):
+    """Arrival times (seconds from 0) of a Poisson process of the given rate (requests/s),
+    from counter-based uniforms (exponential gaps by inversion)."""
+    if rate <= 0 or math.isinf(rate):
+        return np.zeros(count)
+    u = inputs.uniform(seed + 77, count)
+    gaps = -np.log(1.0 - u) / rate
+    return np.cumsum(gaps) - gaps[0]
+
+
+def percentile(values, q):
+    """Nearest-rank percentile (q in [0, 100]) of a non-empty sequence."""
+    v = sorted(values)
+    k = max(0, min(len(v) - 1, int(math.ceil(q / 100.0 * len(v))) - 1))
+    return v[k]
+
+
+class PoolExecutor:
+    """Executor backed by the device pool; builds each request's initial fields on submit."""
+
+    def __init__(self, pool, physics=None):
+        self.pool = pool
+        self.physics = physics or inputs.physics()
+
+    def submit(self, req):
+        f = inputs.request_fields(req, self.physics)
+        return self.pool.submit(f["params"], f["rho0"], f["u0"], f["T0"], req["steps"])
+
+    def run(self):
+        self.pool.run()
+
+    def poll(self, ticket):
+        return self.pool.poll(ticket)
+
+    def collect(self, ticket):
+        return self.pool.collect(ticket)
+
+    def stats(self):
+        return self.pool.stats()
+
+
+def serve(requests, arrivals, executor, clock=time.perf_counter, sleep=time.sleep,
+          keep_results=False):
+    """Run the continuous-batching loop.  Returns a report dict with per-request latencies,
+    p50/p99 time-to-result, aggregate node updates per second and the peak number of requests
+    in flight.  `requests[i]` arrives at `arrivals[i]` seconds after the start."""
+    order = sorted(range(len(requests)), key=lambda i: (arrivals[i], i))
+    pending = collections.deque(order)
+    waiting = []                         # arrived, not yet admitted (arrival order)
+    inflight = {}                        # ticket -> request index
+    latency = {}
+    status = {}
+    results = {}
+    node_updates = 0
+    peak = 0
+    replays = 0
+    t0 = clock()
+    while pending or waiting or inflight:
+        now = clock() - t0
+        while pending and arrivals[pending[0]] <= now:
+            waiting.append(pending.popleft())
+        still = []
+        for i in waiting:                # first fit in arrival order
+            ticket = executor.submit(requests[i])
+            if ticket is None:
+                still.append(i)
+            else:
+                inflight[ticket] = i
+        waiting = still
+        peak = max(peak, len(inflight))
+        if not inflight:
+            if pending:
+                sleep(max(0.0, arrivals[pending[0]] - (clock() - t0)))
+            elif waiting:
+                raise RuntimeError("request %d can never be admitted (larger than the pool)"
+                                   % requests[waiting[0]]["id"])
+            continue
+        executor.run()
+        replays += 1
+        done_now = clock() - t0
+        for ticket in list(inflight):
+            done, st = executor.poll(ticket)
+            if not done:
+                continue
+            i = inflight.pop(ticket)
+            fields, st = executor.collect(ticket)
+            latency[i] = done_now - arrivals[i]
+            status[i] = st
+            if keep_results:
+                results[i] = fields
+            if st == 0:
+                r = requests[i]
+                node_updates += r["edge"] ** 3 * r["steps"]
+    wall = clock() - t0
+    lat = [latency[i] for i in range(len(requests)) if status.get(i) == 0]
+    report = {
+        "requests": len(requests), "completed": len(lat),
+        "failed": sum(1 for s in status.values() if s != 0),
+        "wall_s": wall, "replays": replays, "peak_in_flight": peak,
+        "node_updates": node_updates,
+        "aggregate_mlups": node_updates / wall / 1e6 if wall > 0 else float("nan"),
+        "p50_s": percentile(lat, 50) if lat else None,
+        "p99_s": percentile(lat, 99) if lat else None,
+        "latency_s": [latency.get(i) for i in range(len(requests))],
+        "status": [status.get(i) for i in range(len(requests))],
+    }
+    if keep_results:
+        report["results"] = results
+    return report
+
+
+def one_at_a_time(requests, physics=None, clock=time.perf_counter):
+    """The same requests solved one after another with a single simulation each (lbm_init,
+    lbm_step, lbm_moments, lbm_free): aggregate node updates per second."""
+    from . import lbm
+    physics = physics or inputs.physics()
+    t0 = clock()
+    total = 0
+    for r in requests:
+        f = inputs.request_fields(r, physics)
+        with lbm.Sim(19, f["params"], f["rho0"], f["u0"], f["T0"], storage_bytes=4) as s:
+            s.step(r["steps"])
+            s.moments()
+        total += r["edge"] ** 3 * r["steps"]
+    wall = clock() - t0
+    return {"wall_s": wall, "node_updates": total, "aggregate_mlups": total / wall / 1e6}

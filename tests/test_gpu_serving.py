@@ -1,0 +1,107 @@
+"""The device serving pool: each request's result is the same alone and in a mix of uneven
+lattice sizes (bitwise), matches the single-simulation path and the oracle, admission respects
+the HBM budget, slots are reused while others run, and an unstable request is retired without
+disturbing the others."""
+import numpy as np
+import pytest
+
+from paper_1705_10045_amd import inputs as I
+from paper_1705_10045_amd import lbm, serve
+from parity import describe, rel_errors, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+GIB = 1 << 30
+
+
+def _req(i, edge, steps, kind="droplet", Tr=0.8):
+    return dict(id=i, edge=edge, Tr=Tr, kind=kind, steps=steps, seed=I.SEED + 1 + i, noise=0.01)
+
+
+def _run_pool(reqs, budget=2 * GIB, slots=16, spr=10, arrivals=None):
+    with lbm.Pool(budget, max_slots=slots, steps_per_run=spr) as pool:
+        ex = serve.PoolExecutor(pool)
+        arr = np.zeros(len(reqs)) if arrivals is None else arrivals
+        return serve.serve(reqs, arr, ex, keep_results=True)
+
+
+def test_result_same_alone_and_in_mix():
+    target = _req(0, 32, 57, "droplet", 0.78)
+    others = [_req(1, 48, 33, "slab", 0.9), _req(2, 64, 80, "droplet", 0.72),
+              _req(3, 32, 21, "slab", 0.85), _req(4, 48, 64, "droplet", 0.93)]
+    alone = _run_pool([target])["results"][0]
+    mix = _run_pool(others[:2] + [target] + others[2:])
+    assert mix["completed"] == 5
+    in_mix = mix["results"][2]
+    for k in alone:
+        assert np.array_equal(alone[k], in_mix[k]), k
+
+
+def test_pool_matches_single_simulation_and_oracle():
+    req = _req(5, 32, 40, "slab", 0.8)
+    res = _run_pool([req])["results"][0]
+    f = I.request_fields(req)
+    with lbm.Sim(19, f["params"], f["rho0"], f["u0"], f["T0"], storage_bytes=4) as s:
+        s.step(req["steps"])
+        single = s.moments()
+    for k in res:
+        assert np.array_equal(res[k], single[k]), k
+    o, _ = run_oracle(f, req["steps"])
+    errs = rel_errors(res, o)
+    describe("pool vs oracle", errs)
+    assert max(errs.values()) < 1e-5
+
+
+def test_admission_respects_budget_and_reuses_slots():
+    params = I.physics()
+    f32 = I.request_fields(_req(6, 32, 30))
+    f64 = I.request_fields(_req(7, 64, 30))
+    one32 = 2 * 2 * 19 * 32 ** 3 * 4
+    with lbm.Pool(3 * one32 + (1 << 20), max_slots=8, steps_per_run=10) as pool:
+        t = [pool.submit(params, f32["rho0"], f32["u0"], f32["T0"], 30) for _ in range(4)]
+        assert t[3] is None and all(x is not None for x in t[:3])      # budget binds
+        assert pool.submit(params, f64["rho0"], f64["u0"], f64["T0"], 30) is None
+        st = pool.stats()
+        assert st["bytes_in_use"] <= st["budget"] and st["active"] == 3
+        for _ in range(3):
+            pool.run()
+        assert all(pool.poll(x)[0] for x in t[:3])
+        for x in t[:3]:
+            pool.collect(x)
+        assert pool.stats()["bytes_in_use"] == 0
+        again = pool.submit(params, f32["rho0"], f32["u0"], f32["T0"], 30)
+        assert again is not None
+
+
+def test_unstable_request_is_isolated():
+    good = _req(8, 32, 30, "droplet", 0.8)
+    shape = (24, 24, 24)
+    bad_rho = I.two_phase(I.sphere_mask(shape, 5), 2.3, 0.02)
+    with lbm.Pool(2 * GIB, max_slots=4, steps_per_run=10) as pool:
+        fg = I.request_fields(good)
+        tg = pool.submit(fg["params"], fg["rho0"], fg["u0"], fg["T0"], good["steps"])
+        tb = pool.submit(I.physics(tau=0.501), bad_rho, I.uniform_velocity(shape, (0.3, 0, 0)),
+                         np.full(shape, 0.6), 200)
+        for _ in range(20):
+            pool.run()
+            if pool.poll(tg)[0] and pool.poll(tb)[0]:
+                break
+        assert pool.poll(tb) == (True, lbm.LBM_EUNSTABLE)
+        assert pool.poll(tg) == (True, lbm.LBM_OK)
+        res, st = pool.collect(tg)
+        assert st == lbm.LBM_OK
+        _, stb = pool.collect(tb)
+        assert stb == lbm.LBM_EUNSTABLE
+    alone = _run_pool([good])["results"][0]
+    for k in res:
+        assert np.array_equal(res[k], alone[k])
+
+
+def test_continuous_arrivals_complete():
+    reqs = I.serving_requests(24, steps_range=(20, 120), edges=(32, 48, 64))
+    arr = serve.poisson_arrivals(len(reqs), rate=200.0)
+    rep = _run_pool(reqs, budget=GIB, slots=8, spr=10, arrivals=arr)
+    assert rep["completed"] == 24 and rep["failed"] == 0
+    assert rep["peak_in_flight"] <= 8
+    print("serving: p50 %.3fs p99 %.3fs %.0f MLUPS" % (rep["p50_s"], rep["p99_s"],
+                                                       rep["aggregate_mlups"]), flush=True)
