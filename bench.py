@@ -109,6 +109,46 @@ def copy_probe(gib=1.0, reps=5):
                       "launches": reps}), flush=True)
 
 
+def sweep(sim, stream, n, storage, chunks=(4, 8, 16, 32), steps=40):
+    """Time each launch variant from the same checkpointed state; every variant must reproduce
+    the same fields bit for bit."""
+    import numpy as np
+    import torch
+    from paper_1705_10045_amd import lbm
+    ck = sim.checkpoint()
+    ref = None
+    nvar = 0
+    while True:
+        try:
+            sim.set_launch(nvar, 0)
+            nvar += 1
+        except lbm.LbmError:
+            break
+    for v in range(nvar):
+        for c in chunks:
+            sim.set_launch(v, c)
+            sim.restore(ck)
+            sim.step(5)
+            start = torch.cuda.Event(enable_timing=True)
+            end = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            start.record(stream)
+            sim.step_async(steps)
+            end.record(stream)
+            torch.cuda.synchronize()
+            sim.check()
+            ms = start.elapsed_time(end) / steps
+            m = sim.moments()["rho"]
+            same = ref is None or np.array_equal(m, ref)
+            ref = m if ref is None else ref
+            info = sim.launch_info()
+            print(json.dumps({"variant": v, "tile": [info["tile_x"], info["tile_y"]], "chunk": c,
+                              "workgroups": info["workgroups"], "ms_per_step": round(ms, 4),
+                              "mlups": round(n / ms / 1e3, 1),
+                              "frac": round(BYTES_PER_UPDATE[storage] * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                              "bitwise_equal": bool(same)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +157,10 @@ def main():
     ap.add_argument("--workload", default="droplet128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time every tile variant x z-chunk of the step kernel (tuning)")
+    ap.add_argument("--variant", type=int, default=None)
+    ap.add_argument("--chunk", type=int, default=0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -135,11 +179,18 @@ def main():
 
     case, storage, config = workload(args.workload)
     n = case["rho0"].size
-    stream = torch.cuda.current_stream()
+    # a dedicated stream (default priority): the library enqueues on it and the events below
+    # bracket exactly its launches
+    stream = torch.cuda.Stream()
     print("bench: %s, %d warmup + %d timed steps" % (config["workload"], args.warmup, args.steps),
           file=sys.stderr, flush=True)
     sim = lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"],
                   storage_bytes=storage, stream=stream.cuda_stream)
+    if args.variant is not None or args.chunk:
+        sim.set_launch(args.variant or 0, args.chunk)
+    if args.sweep:
+        sweep(sim, stream, n, storage)
+        return
     info = sim.launch_info()
     sim.step(args.warmup)
 

@@ -126,6 +126,12 @@ const char* lbm_last_error(void);
  * number of workgroups per step (for profiling reports). */
 lbm_status lbm_launch_info(const lbm_sim* sim, int info[4]);
 
+/* Select the tile shape (variant 0 .. n-1; FP32 D3Q19 has several, other configurations one)
+ * and the z-chunk length (0 = automatic) of the fused step kernel.  Results do not depend on
+ * the choice (the per-node arithmetic is the same); only speed does.  LBM_EINVAL for an
+ * unknown variant. */
+lbm_status lbm_set_launch(lbm_sim* sim, int variant, int chunk);
+
 /* Velocity set used by the library (section 2) and the force coefficients of section 3:
  * c[3Q] (integer components), w[Q], G[Q], *alpha.  Returns the dimension D, or LBM_EINVAL
  * for an unsupported Q.  Host only; touches no device. */

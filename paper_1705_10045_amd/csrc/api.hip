@@ -226,12 +226,13 @@ lbm_status validate_fields(const lbm_params& p, const double* rho0, const double
     return LBM_OK;
 }
 
-// Launch geometry: tiles from step_tile, z chunks sized for >= ~1024 workgroups.
-void choose_geometry(lbm_sim* s)
+// Launch geometry: tiles of the selected variant, z chunks sized for >= ~1024 workgroups
+// unless a chunk length is given.
+void choose_geometry(lbm_sim* s, int chunk_request)
 {
     const lbm_params& p = s->p;
     int tx, ty;
-    step_tile(p.lattice, p.storage_bytes, tx, ty);
+    step_tile(p.lattice, p.storage_bytes, s->variant, tx, ty);
     StepGeom& g = s->geom;
     g.nx = p.nx; g.ny = p.ny; g.nz = p.nz;
     g.plane = s->plane;
@@ -245,10 +246,7 @@ void choose_geometry(lbm_sim* s)
         if (want > maxc) want = maxc;
         if (want < 1) want = 1;
         chunk = (int)((p.nz + want - 1) / want);
-        if (const char* e = std::getenv("LBM_CHUNK")) {
-            const int v = std::atoi(e);
-            if (v > 0) chunk = v < p.nz ? v : p.nz;
-        }
+        if (chunk_request > 0) chunk = chunk_request < p.nz ? chunk_request : p.nz;
     }
     g.chunk = chunk;
     g.nchunks = (p.nz + chunk - 1) / chunk;
@@ -276,8 +274,8 @@ lbm_status enqueue_steps(lbm_sim* s, int nsteps)
         return LBM_EDEVICE;
     }
     for (int i = 0; i < nsteps; ++i) {
-        hipError_t e = launch_step(s->p.lattice, s->p.storage_bytes, s->buf[s->cur], s->buf[1 - s->cur],
-                                   s->geom, s->phys, s->aux, s->stream);
+        hipError_t e = launch_step(s->p.lattice, s->p.storage_bytes, s->variant, s->buf[s->cur],
+                                   s->buf[1 - s->cur], s->geom, s->phys, s->aux, s->stream);
         if (e != hipSuccess) return hip_fail(e, "step launch");
         s->cur ^= 1;
         s->step += 1;
@@ -370,7 +368,7 @@ lbm_status lbm_init(const lbm_params* params, const double* rho0, const double* 
         if (e != hipSuccess) { delete s; return hip_fail(e, "hipStreamCreate"); }
         s->own_stream = true;
     }
-    choose_geometry(s);
+    choose_geometry(s, 0);
     const size_t bytes = state_bytes(s->p);
     hipError_t e = hipMalloc(&s->buf[0], bytes);
     if (e == hipSuccess) e = hipMalloc(&s->buf[1], bytes);
@@ -428,6 +426,19 @@ lbm_status lbm_step(lbm_sim* s, int nsteps)
 }
 
 long long lbm_step_count(const lbm_sim* s) { return s ? s->step : -1; }
+
+lbm_status lbm_set_launch(lbm_sim* s, int variant, int chunk)
+{
+    clear_error();
+    if (!s) { set_error("simulation is NULL"); return LBM_EINVAL; }
+    if (variant < 0 || variant >= step_variants(s->p.lattice, s->p.storage_bytes) || chunk < 0) {
+        set_error("launch variant %d / chunk %d not available for this lattice and storage", variant, chunk);
+        return LBM_EINVAL;
+    }
+    s->variant = variant;
+    choose_geometry(s, chunk);
+    return LBM_OK;
+}
 
 lbm_status lbm_launch_info(const lbm_sim* s, int info[4])
 {

@@ -179,33 +179,57 @@ inline unsigned blocks_for(long long n, int threads)
     return (unsigned)((n + threads - 1) / threads);
 }
 
-template <int Q, class S, class R, int TX, int TY>
+template <int Q, class S, class R, int TX, int TY, bool PIPE>
 hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Phys& ph,
                          const StepAux& aux, hipStream_t st)
 {
     const unsigned nblk = (unsigned)(g.ntx * g.nty * g.nchunks);
-    hipLaunchKernelGGL((k_step<Q, S, R, TX, TY>), dim3(nblk), dim3(TX * TY), 0, st,
+    hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, PIPE>), dim3(nblk), dim3(TX * TY), 0, st,
                        (const S*)src, (S*)dst, g, ph, aux);
     return hipGetLastError();
 }
 
 }  // namespace
 
-// Tile shapes per (lattice, storage): FP64 halves the tile height to keep the LDS rings of
-// two workgroups within one CU's 160 KB.
-void step_tile(int Q, int storage_bytes, int& tx, int& ty)
+// Tile shapes of the fused step.  Variant 0 is the default per (lattice, storage); the others
+// exist for FP32 D3Q19 (the bandwidth-critical path) and are selected for tuning.  Per-node
+// arithmetic does not depend on the tile shape, so every variant gives bitwise-identical
+// results.
+struct TileShape { int tx, ty; bool pipe; };
+static const TileShape kVariants19f[] = {{32, 8, true},  {32, 8, false}, {64, 4, true},
+                                         {64, 4, false}, {32, 16, true}, {16, 16, true}};
+constexpr int kNumVariants19f = sizeof(kVariants19f) / sizeof(kVariants19f[0]);
+
+int step_variants(int Q, int storage_bytes) { return (Q == 19 && storage_bytes == 4) ? kNumVariants19f : 1; }
+
+void step_tile(int Q, int storage_bytes, int variant, int& tx, int& ty)
 {
+    if (Q == 19 && storage_bytes == 4 && variant >= 0 && variant < kNumVariants19f) {
+        tx = kVariants19f[variant].tx;
+        ty = kVariants19f[variant].ty;
+        return;
+    }
     tx = 32;
     ty = (Q == 19 && storage_bytes == 8) ? 4 : 8;
 }
 
-hipError_t launch_step(int Q, int storage_bytes, const void* src, void* dst, const StepGeom& g,
-                       const Phys& ph, const StepAux& aux, hipStream_t st)
+hipError_t launch_step(int Q, int storage_bytes, int variant, const void* src, void* dst,
+                       const StepGeom& g, const Phys& ph, const StepAux& aux, hipStream_t st)
 {
-    if (Q == 19 && storage_bytes == 4) return launch_step_t<19, float, float, 32, 8>(src, dst, g, ph, aux, st);
-    if (Q == 19 && storage_bytes == 8) return launch_step_t<19, double, double, 32, 4>(src, dst, g, ph, aux, st);
-    if (Q == 9 && storage_bytes == 4) return launch_step_t<9, float, float, 32, 8>(src, dst, g, ph, aux, st);
-    if (Q == 9 && storage_bytes == 8) return launch_step_t<9, double, double, 32, 8>(src, dst, g, ph, aux, st);
+    if (Q == 19 && storage_bytes == 4) {
+        switch (variant) {
+        case 0: return launch_step_t<19, float, float, 32, 8, true>(src, dst, g, ph, aux, st);
+        case 1: return launch_step_t<19, float, float, 32, 8, false>(src, dst, g, ph, aux, st);
+        case 2: return launch_step_t<19, float, float, 64, 4, true>(src, dst, g, ph, aux, st);
+        case 3: return launch_step_t<19, float, float, 64, 4, false>(src, dst, g, ph, aux, st);
+        case 4: return launch_step_t<19, float, float, 32, 16, true>(src, dst, g, ph, aux, st);
+        case 5: return launch_step_t<19, float, float, 16, 16, true>(src, dst, g, ph, aux, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (Q == 19 && storage_bytes == 8) return launch_step_t<19, double, double, 32, 4, false>(src, dst, g, ph, aux, st);
+    if (Q == 9 && storage_bytes == 4) return launch_step_t<9, float, float, 32, 8, true>(src, dst, g, ph, aux, st);
+    if (Q == 9 && storage_bytes == 8) return launch_step_t<9, double, double, 32, 8, false>(src, dst, g, ph, aux, st);
     return hipErrorInvalidValue;
 }
 

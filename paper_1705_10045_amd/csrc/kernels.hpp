@@ -23,9 +23,10 @@ struct StepAux {
     int* err;                            // device error word (atomicOr)
 };
 
-void step_tile(int Q, int storage_bytes, int& tx, int& ty);
-hipError_t launch_step(int Q, int storage_bytes, const void* src, void* dst, const StepGeom& g,
-                       const Phys& ph, const StepAux& aux, hipStream_t st);
+int step_variants(int Q, int storage_bytes);
+void step_tile(int Q, int storage_bytes, int variant, int& tx, int& ty);
+hipError_t launch_step(int Q, int storage_bytes, int variant, const void* src, void* dst,
+                       const StepGeom& g, const Phys& ph, const StepAux& aux, hipStream_t st);
 hipError_t launch_init(int Q, int storage_bytes, void* buf, const double* rho0, const double* u0,
                        const double* T0, int nx, int ny, int nz, long long plane, double c_v,
                        hipStream_t st);

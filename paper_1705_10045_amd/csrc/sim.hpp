@@ -25,6 +25,7 @@ struct lbm_sim {
     double* d_scratch = nullptr;         // moment scratch (7n doubles), allocated on first use
     int red_blocks = 1;
     int tile_x = 0, tile_y = 0;
+    int variant = 0;                     // tile shape of the fused step (see step_tile)
 };
 
 namespace lbm {

@@ -12,14 +12,20 @@
 // Work decomposition: a workgroup owns a TX x TY column of nodes and marches through a chunk
 // of z planes.  Per z iteration it runs three stages separated by barriers:
 //   M: pull 2Q populations and form rho, j, E, T, p, Phi for plane zm on the tile plus a
-//      2-node halo (LDS ring of 4 planes);
+//      2-node halo (LDS rings);
 //   F: force and u* for plane zm-1 on the tile plus a 1-node halo (LDS ring);
 //   C: energy source, collisions and the store for plane zm-2 on the tile.
 // D2Q9 runs the same code with a single plane (no z halo, no lag between the stages).
+// With PIPE the populations of the next plane's M stage are requested right after the
+// current plane's sums, so they are in flight while the F and C stages run.
 //
 // Per-node quantities of the tile's own nodes (rho, j, E, T, p, F) stay in registers between
 // the stages; populations are re-read for the collision (they were pulled two planes earlier
 // by this workgroup, so the re-read is served by the caches).
+//
+// Arithmetic: moments, EOS, Phi and the force in FP64 (the force is a small difference of
+// Phi^2 values); u*, the energy source and the collision in R; the rest populations close the
+// mass and energy balances of the collision in FP64 over the stored values.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -72,7 +78,7 @@ __device__ __forceinline__ void region_slot(int s, int& rx, int& ry)
 
 // One workgroup's share of a step: tile `lb` (x fastest, then y, then z chunk) of the box
 // described by g.  Must be called by all TX*TY threads of the workgroup.
-template <int Q, class S, class R, int TX, int TY>
+template <int Q, class S, class R, int TX, int TY, bool PIPE>
 __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restrict__ dst,
                                           const StepGeom& g, const Phys& ph, const StepAux& aux,
                                           const int lb)
@@ -83,15 +89,21 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     constexpr int NT = TX * TY;
     constexpr int EX = TX + 4, EY = TY + 4, NE = EX * EY;   // moments: tile + 2-halo
     constexpr int FX = TX + 2, FY = TY + 2, NF = FX * FY;   // force/u*: tile + 1-halo
-    constexpr int RING = (D == 3) ? 4 : 1;
+    constexpr int RING = (D == 3) ? 4 : 1;  // planes of Phi, rho, T held (zc-1 .. zc+2)
+    constexpr int JR = (D == 3) ? 2 : 1;    // planes of j held (zf, zf+1)
+    constexpr int UR = (D == 3) ? 3 : 1;    // planes of u* held (zc-1 .. zc+1)
     constexpr int ME = (NE + NT - 1) / NT;
     constexpr int MF = (NF + NT - 1) / NT;
 
-    __shared__ double sPhi[RING][NE];   // Phi in FP64: the force is a small difference of Phi^2
+    __shared__ double sPhi[RING][NE];
     __shared__ R sRho[RING][NE];
     __shared__ R sT[RING][NE];
-    __shared__ R sJ[3][RING][NE];
-    __shared__ R sU[3][RING][NF];
+    __shared__ R sJ[3][JR][NE];
+    __shared__ R sU[3][UR][NF];
+
+    auto ring = [](int z) { return (z + 4) & (RING - 1); };   // z >= -4
+    auto jring = [](int z) { return (z + 4) & (JR - 1); };
+    auto uring = [](int z) { return (z + 6) % UR; };          // z >= -6
 
     const int tid = threadIdx.x;
     const int tix = lb % g.ntx;
@@ -109,6 +121,8 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     for (int r = 0; r < ME; ++r) {
         const int s = tid + r * NT;
         m_e[r] = -1;
+        m_x[r][0] = m_x[r][1] = m_x[r][2] = 0;
+        m_y[r][0] = m_y[r][1] = m_y[r][2] = 0;
         if (s < NE) {
             int ex, ey;
             region_slot<TX, TY, 2>(s, ex, ey);
@@ -145,9 +159,14 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     const int xs[3] = {m_x[0][0], m_x[0][1], m_x[0][2]};   // slot 0 is the own node
     const int ys[3] = {m_y[0][0], m_y[0][1], m_y[0][2]};
 
-    const R omega = R(ph.omega), omega_E = R(ph.omega_E);
+    const R omega_E = R(ph.omega_E);
+    const R keepN = R(1.0 - ph.omega), keepG = R(1.0 - ph.omega_E);
+    // with tau = 1 the BGK term of N' no longer depends on N_k (N' = Neq(rho, v)): the
+    // density populations are then not re-read (keepN * (0 - rho Pu) adds an exact zero)
+    const bool needN = keepN != R(0);
     const R cond_half = R(ph.cond_half);
     const unsigned flags = ph.flags;
+    const bool pseudo = (flags & kPseudo) != 0;
 
     // register ring of the own node's moments: [0] newest plane ... [ZH] plane being collided
     double o_rho[ZH + 1], o_E[ZH + 1], o_p[ZH + 1];
@@ -159,10 +178,9 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         o_E[q] = 1.0; o_T[q] = R(1); o_p[q] = 0.0;
     }
 
-    const int niter = (z1 - z0) + 2 * ZH;
-    for (int it = 0; it < niter; ++it) {
-        const int zm = z0 - ZH + it;
-        const int sm = (zm + 4) & (RING - 1);
+    // populations of the moment-stage slots for one plane
+    S pn[ME][Q], pe[ME][Q];
+    auto load_plane = [&](int zm) {
         int zoff[3];
         if constexpr (D == 3) {
             zoff[0] = wrap_index(zm - 1, g.nz) * nxy;
@@ -171,6 +189,26 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         } else {
             zoff[0] = zoff[1] = zoff[2] = 0;
         }
+#pragma unroll
+        for (int r = 0; r < ME; ++r) {
+            if (m_e[r] < 0) continue;
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                const long long off = (long long)zoff[1 - L::cz[k]] + m_y[r][1 - L::cy[k]] +
+                                      m_x[r][1 - L::cx[k]];
+                pn[r][k] = src[(long long)k * g.plane + off];
+                pe[r][k] = src[(long long)(Q + k) * g.plane + off];
+            }
+        }
+    };
+
+    const int niter = (z1 - z0) + 2 * ZH;
+    if constexpr (PIPE) load_plane(z0 - ZH);
+    for (int it = 0; it < niter; ++it) {
+        const int zm = z0 - ZH + it;
+        const int sm = ring(zm);
+        const int sj = jring(zm);
+        if constexpr (!PIPE) load_plane(zm);
 
         // ---------------- M: moments, EOS, Phi on the tile + 2-halo of plane zm
 #pragma unroll
@@ -180,12 +218,9 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             double dr = 0.0, djx = 0.0, djy = 0.0, djz = 0.0, dE = 0.0;
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
-                const long long off = (long long)zoff[1 - L::cz[k]] + m_y[r][1 - L::cy[k]] +
-                                      m_x[r][1 - L::cx[k]];
-                const double n = double(src[(long long)k * g.plane + off]);
-                const double e = double(src[(long long)(Q + k) * g.plane + off]);
+                const double n = double(pn[r][k]);
                 dr += n;
-                dE += e;
+                dE += double(pe[r][k]);
                 if (L::cx[k] == 1) djx += n; else if (L::cx[k] == -1) djx -= n;
                 if (L::cy[k] == 1) djy += n; else if (L::cy[k] == -1) djy -= n;
                 if (L::cz[k] == 1) djz += n; else if (L::cz[k] == -1) djz -= n;
@@ -200,14 +235,14 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
                 atomicOr(aux.err, 1);
                 phi2 = 0.0;
             }
-            const R rho = R(dr), jx = R(djx), jy = R(djy), jz = R(djz), T = R(dT);
+            const R rho = R(dr), T = R(dT);
             const int e = m_e[r];
             sPhi[sm][e] = sqrt(phi2);
             sRho[sm][e] = rho;
             sT[sm][e] = T;
-            sJ[0][sm][e] = jx;
-            sJ[1][sm][e] = jy;
-            sJ[2][sm][e] = jz;
+            sJ[0][sj][e] = R(djx);
+            sJ[1][sj][e] = R(djy);
+            sJ[2][sj][e] = R(djz);
             if (r == 0) {
 #pragma unroll
                 for (int q = ZH; q > 0; --q) {
@@ -215,18 +250,20 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
                     o_jz[q] = o_jz[q - 1]; o_E[q] = o_E[q - 1]; o_T[q] = o_T[q - 1];
                     o_p[q] = o_p[q - 1];
                 }
-                o_rho[0] = dr; o_jx[0] = jx; o_jy[0] = jy; o_jz[0] = jz;
+                o_rho[0] = dr; o_jx[0] = R(djx); o_jy[0] = R(djy); o_jz[0] = R(djz);
                 o_E[0] = dE; o_T[0] = T; o_p[0] = p;
             }
+        }
+        if constexpr (PIPE) {
+            if (it + 1 < niter) load_plane(zm + 1);
         }
         __syncthreads();
 
         // ---------------- F: force and u* on the tile + 1-halo of plane zf = zm - ZH/2
         if (it >= ZH) {
             const int zf = zm - ZH / 2;
-            const int sf = (zf + 4) & (RING - 1);
-            const int sfm = (zf + 3) & (RING - 1);
-            const int sfp = (zf + 5) & (RING - 1);
+            const int sf = ring(zf), sfm = ring(zf - 1), sfp = ring(zf + 1);
+            const int sjf = jring(zf), suf = uring(zf);
 #pragma unroll
             for (int r = 0; r < MF; ++r) {
                 if (f_f[r] < 0) continue;
@@ -252,9 +289,9 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
                 const R Fz = R((ph.A * s1z + b * s2z) * ph.inv_alpha);
                 const R rho = sRho[sf][e];
                 const int f = f_f[r];
-                sU[0][sf][f] = (sJ[0][sf][e] + R(0.5) * Fx) / rho;
-                sU[1][sf][f] = (sJ[1][sf][e] + R(0.5) * Fy) / rho;
-                sU[2][sf][f] = (sJ[2][sf][e] + R(0.5) * Fz) / rho;
+                sU[0][suf][f] = (sJ[0][sjf][e] + R(0.5) * Fx) / rho;
+                sU[1][suf][f] = (sJ[1][sjf][e] + R(0.5) * Fy) / rho;
+                sU[2][suf][f] = (sJ[2][sjf][e] + R(0.5) * Fz) / rho;
                 if (r == 0) {
                     fprev[0] = fcur[0]; fprev[1] = fcur[1]; fprev[2] = fcur[2];
                     fcur[0] = Fx; fcur[1] = Fy; fcur[2] = Fz;
@@ -266,9 +303,25 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         // ---------------- C: energy source, collisions, store for plane zc = zm - ZH
         if (it >= 2 * ZH && own_in_xy) {
             const int zc = zm - ZH;
-            const int sc = (zc + 4) & (RING - 1);
-            const int scm = (zc + 3) & (RING - 1);
-            const int scp = (zc + 5) & (RING - 1);
+            const int sc = ring(zc), scm = ring(zc - 1), scp = ring(zc + 1);
+            const int suc = uring(zc), sucm = uring(zc - 1), sucp = uring(zc + 1);
+            const int zoc = wrap_index(zc, g.nz) * nxy;
+            const int zpull[3] = {wrap_index(zc - 1, g.nz) * nxy, zoc,
+                                  wrap_index(zc + 1, g.nz) * nxy};
+            const long long own = (long long)zoc + oy * g.nx + ox;
+
+            // populations of the own node (moving directions; the rest ones follow from the
+            // balances below)
+            R pk_n[Q], pk_e[Q];
+            pk_n[0] = pk_e[0] = R(0);
+#pragma unroll
+            for (int k = 1; k < Q; ++k) {
+                const long long off = (long long)(D == 3 ? zpull[1 - L::cz[k]] : zoc) +
+                                      ys[1 - L::cy[k]] + xs[1 - L::cx[k]];
+                pk_e[k] = R(src[(long long)(Q + k) * g.plane + off]);
+                pk_n[k] = needN ? R(src[(long long)k * g.plane + off]) : R(0);
+            }
+
             const double rho_d = o_rho[ZH], E_d = o_E[ZH];
             const R rho = R(rho_d), E = R(E_d), T = o_T[ZH];
             const double p = o_p[ZH];
@@ -277,9 +330,9 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             const R dux = Fo[0] / rho, duy = Fo[1] / rho, duz = Fo[2] / rho;
 
             // div u* by central differences on each axis (section 6.2)
-            R div = R(0.5) * (sU[0][sc][of + 1] - sU[0][sc][of - 1]) +
-                    R(0.5) * (sU[1][sc][of + FX] - sU[1][sc][of - FX]);
-            if constexpr (D == 3) div += R(0.5) * (sU[2][scp][of] - sU[2][scm][of]);
+            R div = R(0.5) * (sU[0][suc][of + 1] - sU[0][suc][of - 1]) +
+                    R(0.5) * (sU[1][suc][of + FX] - sU[1][suc][of - FX]);
+            if constexpr (D == 3) div += R(0.5) * (sU[2][sucp][of] - sU[2][sucm][of]);
 
             R dE = R(0);
             if (flags & kWork) dE -= R(p) * div;
@@ -305,15 +358,9 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             }
             const R dEoE = dE / E;
 
-            const int zoc = wrap_index(zc, g.nz) * nxy;
-            const int zpull[3] = {wrap_index(zc - 1, g.nz) * nxy, zoc,
-                                  wrap_index(zc + 1, g.nz) * nxy};
-            const long long own = (long long)zoc + oy * g.nx + ox;
             const R vx = ux + dux, vy = uy + duy, vz = uz + duz;
             const R uu = ux * ux + uy * uy + uz * uz;
             const R vv = vx * vx + vy * vy + vz * vz;
-            const R keepN = R(1) - omega, keepG = R(1) - omega_E;
-            const bool pseudo = (flags & kPseudo) != 0;
             // The collision conserves mass and changes the energy by exactly dE (the BGK,
             // EDM and pseudoforce increments sum to zero; dg(1) sums to dE).  The moving
             // directions are computed from the equilibria and the rest populations close the
@@ -322,18 +369,15 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             double sumN = 0.0, sumG = 0.0;
 #pragma unroll
             for (int k = 1; k < Q; ++k) {
-                const long long off = (long long)(D == 3 ? zpull[1 - L::cz[k]] : zoc) +
-                                      ys[1 - L::cy[k]] + xs[1 - L::cx[k]];
-                const R n = R(src[(long long)k * g.plane + off]);
-                const R e = R(src[(long long)(Q + k) * g.plane + off]);
                 const R w = R(weight<Q>(k));
                 const R cu = R(L::cx[k]) * ux + R(L::cy[k]) * uy + R(L::cz[k]) * uz;
                 const R cv = R(L::cx[k]) * vx + R(L::cy[k]) * vy + R(L::cz[k]) * vz;
                 const R Pu = eq_poly(w, cu, uu);
                 const R Pv = eq_poly(w, cv, vv);
                 // N' = N + (Neq(u) - N)/tau + Neq(v) - Neq(u)      (eq:lbe, eq:edm)
-                const R nn = rho * Pv + keepN * (n - rho * Pu);
+                const R nn = rho * Pv + keepN * (pk_n[k] - rho * Pu);
                 // g' = g + (geq(u) - g)/tau_E + g dE/E [+ geq(v) - geq(u)]   (eq:gk, section 4)
+                const R e = pk_e[k];
                 const R gn = pseudo ? E * Pv + keepG * (e - E * Pu) + e * dEoE
                                     : omega_E * E * Pu + keepG * e + e * dEoE;
                 const S nn_s = S(nn), gn_s = S(gn);
@@ -349,12 +393,13 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     }
 }
 
-template <int Q, class S, class R, int TX, int TY>
+template <int Q, class S, class R, int TX, int TY, bool PIPE>
 __global__ void __launch_bounds__(TX* TY)
 k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const Phys ph,
        const StepAux aux)
 {
-    step_tile<Q, S, R, TX, TY>(src, dst, g, ph, aux, xcd_logical_block(blockIdx.x, gridDim.x));
+    step_tile<Q, S, R, TX, TY, PIPE>(src, dst, g, ph, aux,
+                                     xcd_logical_block(blockIdx.x, gridDim.x));
 }
 
 }  // namespace lbm

@@ -61,6 +61,7 @@ _SIGNATURES = [
     ("lbm_free", _ST, [_P]),
     ("lbm_last_error", ctypes.c_char_p, []),
     ("lbm_launch_info", _ST, [_P, ctypes.POINTER(ctypes.c_int)]),
+    ("lbm_set_launch", _ST, [_P, ctypes.c_int, ctypes.c_int]),
     ("lbm_lattice_info", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D, _D, _D]),
     ("lbm_coexistence", _ST, [ctypes.c_double, _D, _D]),
     ("lbm_pool_create", _ST, [ctypes.c_size_t, ctypes.c_int, ctypes.c_int, _P, ctypes.POINTER(_P)]),
@@ -201,6 +202,10 @@ def lbm_launch_info(h):
     return {"tile_x": info[0], "tile_y": info[1], "chunk": info[2], "workgroups": info[3]}
 
 
+def lbm_set_launch(h, variant, chunk=0):
+    return _check(lib().lbm_set_launch(h, int(variant), int(chunk)))
+
+
 def lbm_lattice_info(Q):
     c = (ctypes.c_int * (3 * Q))()
     w = np.zeros(Q)
@@ -254,6 +259,9 @@ class Sim:
 
     def launch_info(self):
         return lbm_launch_info(self._h)
+
+    def set_launch(self, variant, chunk=0):
+        lbm_set_launch(self._h, variant, chunk)
 
     @property
     def step_count(self):

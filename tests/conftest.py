@@ -17,3 +17,14 @@ def pytest_configure(config):
 def orc():
     import oracle
     return oracle
+
+
+@pytest.hookimpl(hookwrapper=True)
+def pytest_runtest_makereport(item, call):
+    """A device error (LBM_EDEVICE: the HIP runtime reported a fault) ends the session at
+    once, so no further test touches a faulted GPU; ordinary failures let the run continue."""
+    outcome = yield
+    if call.excinfo is not None:
+        exc = call.excinfo.value
+        if type(exc).__name__ == "LbmError" and getattr(exc, "status", None) == -4:
+            pytest.exit("device error in %s: %s" % (item.nodeid, exc), returncode=3)
