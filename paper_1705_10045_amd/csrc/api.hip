@@ -240,12 +240,15 @@ void choose_geometry(lbm_sim* s, int chunk_request)
     g.nty = (p.ny + ty - 1) / ty;
     int chunk = p.nz;
     if (p.lattice == 19) {
+        // about two workgroups per compute unit (512), z chunks of at most 32 planes: longer
+        // chunks re-read fewer halo planes, more workgroups balance the load
         const long long cols = (long long)g.ntx * g.nty;
-        long long want = (1024 + cols - 1) / cols;
-        long long maxc = p.nz / 4 > 0 ? p.nz / 4 : 1;
+        long long want = (512 + cols - 1) / cols;
+        const long long maxc = p.nz / 4 > 0 ? p.nz / 4 : 1;
         if (want > maxc) want = maxc;
         if (want < 1) want = 1;
         chunk = (int)((p.nz + want - 1) / want);
+        if (chunk > 32) chunk = 32;
         if (chunk_request > 0) chunk = chunk_request < p.nz ? chunk_request : p.nz;
     }
     g.chunk = chunk;

@@ -179,25 +179,38 @@ inline unsigned blocks_for(long long n, int threads)
     return (unsigned)((n + threads - 1) / threads);
 }
 
+// Buffer-resource addressing needs every byte offset of the two population sets in 32 bits.
+inline bool fits_buffer(const StepGeom& g, int Q, int storage_bytes)
+{
+    return (unsigned long long)g.plane * 2ull * Q * storage_bytes < (1ull << 32);
+}
+
 template <int Q, class S, class R, int TX, int TY, bool PIPE>
 hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Phys& ph,
                          const StepAux& aux, hipStream_t st)
 {
     const unsigned nblk = (unsigned)(g.ntx * g.nty * g.nchunks);
-    hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, PIPE>), dim3(nblk), dim3(TX * TY), 0, st,
+    if constexpr (sizeof(S) == 4) {
+        if (fits_buffer(g, Q, 4)) {
+            hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, PIPE, true>), dim3(nblk), dim3(TX * TY), 0,
+                               st, (const S*)src, (S*)dst, g, ph, aux);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, PIPE, false>), dim3(nblk), dim3(TX * TY), 0, st,
                        (const S*)src, (S*)dst, g, ph, aux);
     return hipGetLastError();
 }
 
 }  // namespace
 
-// Tile shapes of the fused step.  Variant 0 is the default per (lattice, storage); the others
-// exist for FP32 D3Q19 (the bandwidth-critical path) and are selected for tuning.  Per-node
-// arithmetic does not depend on the tile shape, so every variant gives bitwise-identical
-// results.
+// Launch shapes of the fused step.  Variant 0 is the default per (lattice, storage); the others
+// exist for FP32 D3Q19 (the bandwidth-critical path) and are selected for tuning.  Tile shape
+// and prefetching do not change the per-node arithmetic, so every variant gives
+// bitwise-identical results.
 struct TileShape { int tx, ty; bool pipe; };
-static const TileShape kVariants19f[] = {{32, 8, true},  {32, 8, false}, {64, 4, true},
-                                         {64, 4, false}, {32, 16, true}, {16, 16, true}};
+static const TileShape kVariants19f[] = {
+    {32, 8, false}, {32, 8, true}, {64, 4, true}, {32, 16, true}, {16, 16, true}};
 constexpr int kNumVariants19f = sizeof(kVariants19f) / sizeof(kVariants19f[0]);
 
 int step_variants(int Q, int storage_bytes) { return (Q == 19 && storage_bytes == 4) ? kNumVariants19f : 1; }
@@ -218,12 +231,11 @@ hipError_t launch_step(int Q, int storage_bytes, int variant, const void* src, v
 {
     if (Q == 19 && storage_bytes == 4) {
         switch (variant) {
-        case 0: return launch_step_t<19, float, float, 32, 8, true>(src, dst, g, ph, aux, st);
-        case 1: return launch_step_t<19, float, float, 32, 8, false>(src, dst, g, ph, aux, st);
+        case 0: return launch_step_t<19, float, float, 32, 8, false>(src, dst, g, ph, aux, st);
+        case 1: return launch_step_t<19, float, float, 32, 8, true>(src, dst, g, ph, aux, st);
         case 2: return launch_step_t<19, float, float, 64, 4, true>(src, dst, g, ph, aux, st);
-        case 3: return launch_step_t<19, float, float, 64, 4, false>(src, dst, g, ph, aux, st);
-        case 4: return launch_step_t<19, float, float, 32, 16, true>(src, dst, g, ph, aux, st);
-        case 5: return launch_step_t<19, float, float, 16, 16, true>(src, dst, g, ph, aux, st);
+        case 3: return launch_step_t<19, float, float, 32, 16, true>(src, dst, g, ph, aux, st);
+        case 4: return launch_step_t<19, float, float, 16, 16, true>(src, dst, g, ph, aux, st);
         default: return hipErrorInvalidValue;
         }
     }

@@ -76,13 +76,53 @@ __device__ __forceinline__ void region_slot(int s, int& rx, int& ry)
     rx = c < HALO ? c : RW - 2 * HALO + c;
 }
 
+// Access to population (set*Q + k) at node i of the two buffers.  With BUF the state (< 4 GB)
+// is addressed through buffer resources: the node offset is a 32-bit per-lane byte offset and
+// the plane offset of the population a scalar offset, so no per-access 64-bit address
+// arithmetic is spent.  Otherwise plain global pointers.
+template <class S, bool BUF>
+struct PopIO;
+
+template <class S>
+struct PopIO<S, false> {
+    const S* __restrict__ src;
+    S* __restrict__ dst;
+    long long plane;
+    __device__ PopIO(const S* s, S* d, long long p, int) : src(s), dst(d), plane(p) {}
+    __device__ __forceinline__ S load(int pk, int i) const { return src[(long long)pk * plane + i]; }
+    __device__ __forceinline__ void store(int pk, int i, S v) const { dst[(long long)pk * plane + i] = v; }
+};
+
+template <>
+struct PopIO<float, true> {
+    __amdgpu_buffer_rsrc_t rs, rd;
+    int plane_bytes;
+    __device__ PopIO(const float* s, float* d, long long p, int npk)
+    {
+        const unsigned bytes = (unsigned)(p * npk * 4);
+        rs = __builtin_amdgcn_make_buffer_rsrc((void*)s, (short)0, (int)bytes, 0x00020000);
+        rd = __builtin_amdgcn_make_buffer_rsrc((void*)d, (short)0, (int)bytes, 0x00020000);
+        plane_bytes = (int)(p * 4);
+    }
+    __device__ __forceinline__ float load(int pk, int i) const
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, i * 4, pk * plane_bytes, 0));
+    }
+    __device__ __forceinline__ void store(int pk, int i, float v) const
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rd, i * 4, pk * plane_bytes, 0);
+    }
+};
+
 // One workgroup's share of a step: tile `lb` (x fastest, then y, then z chunk) of the box
 // described by g.  Must be called by all TX*TY threads of the workgroup.
-template <int Q, class S, class R, int TX, int TY, bool PIPE>
+template <int Q, class S, class R, int TX, int TY, bool PIPE, bool BUF>
 __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restrict__ dst,
                                           const StepGeom& g, const Phys& ph, const StepAux& aux,
                                           const int lb)
 {
+    static_assert(!BUF || sizeof(S) == 4, "buffer addressing is used for FP32 populations");
+    PopIO<S, BUF> io(src, dst, g.plane, 2 * Q);
     using L = Lattice<Q>;
     constexpr int D = L::D;
     constexpr int ZH = (D == 3) ? 2 : 0;    // lead of the moment stage over the collision
@@ -192,12 +232,17 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
 #pragma unroll
         for (int r = 0; r < ME; ++r) {
             if (m_e[r] < 0) continue;
+            // the nine (y, z) rows the pulls of this slot read from
+            int row[3][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) row[a][b] = zoff[a] + m_y[r][b];
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
-                const long long off = (long long)zoff[1 - L::cz[k]] + m_y[r][1 - L::cy[k]] +
-                                      m_x[r][1 - L::cx[k]];
-                pn[r][k] = src[(long long)k * g.plane + off];
-                pe[r][k] = src[(long long)(Q + k) * g.plane + off];
+                const int off = row[1 - L::cz[k]][1 - L::cy[k]] + m_x[r][1 - L::cx[k]];
+                pn[r][k] = io.load(k, off);
+                pe[r][k] = io.load(Q + k, off);
             }
         }
     };
@@ -268,7 +313,7 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             for (int r = 0; r < MF; ++r) {
                 if (f_f[r] < 0) continue;
                 const int e = f_e[r];
-                // force of section 3 in FP64
+                // force of section 3 in FP64 (a small difference of Phi^2 values)
                 double s1x = 0, s1y = 0, s1z = 0, s2x = 0, s2y = 0, s2z = 0;
 #pragma unroll
                 for (int k = 1; k < Q; ++k) {
@@ -283,15 +328,16 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
                     if (L::cz[k] == 1) { s1z += gph2; s2z += gph; }
                     else if (L::cz[k] == -1) { s1z -= gph2; s2z -= gph; }
                 }
-                const double b = (1.0 - 2.0 * ph.A) * sPhi[sf][e];
-                const R Fx = R((ph.A * s1x + b * s2x) * ph.inv_alpha);
-                const R Fy = R((ph.A * s1y + b * s2y) * ph.inv_alpha);
-                const R Fz = R((ph.A * s1z + b * s2z) * ph.inv_alpha);
-                const R rho = sRho[sf][e];
+                const double Am = ph.A, ia = ph.inv_alpha;
+                const double b = (1.0 - 2.0 * Am) * sPhi[sf][e];
+                const R Fx = R((Am * s1x + b * s2x) * ia);
+                const R Fy = R((Am * s1y + b * s2y) * ia);
+                const R Fz = R((Am * s1z + b * s2z) * ia);
+                const R inv_rho = R(1) / sRho[sf][e];
                 const int f = f_f[r];
-                sU[0][suf][f] = (sJ[0][sjf][e] + R(0.5) * Fx) / rho;
-                sU[1][suf][f] = (sJ[1][sjf][e] + R(0.5) * Fy) / rho;
-                sU[2][suf][f] = (sJ[2][sjf][e] + R(0.5) * Fz) / rho;
+                sU[0][suf][f] = (sJ[0][sjf][e] + R(0.5) * Fx) * inv_rho;
+                sU[1][suf][f] = (sJ[1][sjf][e] + R(0.5) * Fy) * inv_rho;
+                sU[2][suf][f] = (sJ[2][sjf][e] + R(0.5) * Fz) * inv_rho;
                 if (r == 0) {
                     fprev[0] = fcur[0]; fprev[1] = fcur[1]; fprev[2] = fcur[2];
                     fcur[0] = Fx; fcur[1] = Fy; fcur[2] = Fz;
@@ -308,26 +354,33 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             const int zoc = wrap_index(zc, g.nz) * nxy;
             const int zpull[3] = {wrap_index(zc - 1, g.nz) * nxy, zoc,
                                   wrap_index(zc + 1, g.nz) * nxy};
-            const long long own = (long long)zoc + oy * g.nx + ox;
+            const int own = zoc + oy * g.nx + ox;
 
             // populations of the own node (moving directions; the rest ones follow from the
             // balances below)
             R pk_n[Q], pk_e[Q];
             pk_n[0] = pk_e[0] = R(0);
+            {
+                int row[3][3];
 #pragma unroll
-            for (int k = 1; k < Q; ++k) {
-                const long long off = (long long)(D == 3 ? zpull[1 - L::cz[k]] : zoc) +
-                                      ys[1 - L::cy[k]] + xs[1 - L::cx[k]];
-                pk_e[k] = R(src[(long long)(Q + k) * g.plane + off]);
-                pk_n[k] = needN ? R(src[(long long)k * g.plane + off]) : R(0);
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) row[a][b] = (D == 3 ? zpull[a] : zoc) + ys[b];
+#pragma unroll
+                for (int k = 1; k < Q; ++k) {
+                    const int off = row[1 - L::cz[k]][1 - L::cy[k]] + xs[1 - L::cx[k]];
+                    pk_e[k] = R(io.load(Q + k, off));
+                    pk_n[k] = needN ? R(io.load(k, off)) : R(0);
+                }
             }
 
             const double rho_d = o_rho[ZH], E_d = o_E[ZH];
             const R rho = R(rho_d), E = R(E_d), T = o_T[ZH];
             const double p = o_p[ZH];
             const R* Fo = (ZH > 0) ? fprev : fcur;
-            const R ux = o_jx[ZH] / rho, uy = o_jy[ZH] / rho, uz = o_jz[ZH] / rho;
-            const R dux = Fo[0] / rho, duy = Fo[1] / rho, duz = Fo[2] / rho;
+            const R inv_rho = R(1) / rho;
+            const R ux = o_jx[ZH] * inv_rho, uy = o_jy[ZH] * inv_rho, uz = o_jz[ZH] * inv_rho;
+            const R dux = Fo[0] * inv_rho, duy = Fo[1] * inv_rho, duz = Fo[2] * inv_rho;
 
             // div u* by central differences on each axis (section 6.2)
             R div = R(0.5) * (sU[0][suc][of + 1] - sU[0][suc][of - 1]) +
@@ -367,13 +420,15 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             // balances in FP64 over the values actually stored, so rounding of the lattice
             // weights cannot create mass or energy.
             double sumN = 0.0, sumG = 0.0;
+            const R base_u = R(1) - R(1.5) * uu, base_v = R(1) - R(1.5) * vv;
 #pragma unroll
             for (int k = 1; k < Q; ++k) {
                 const R w = R(weight<Q>(k));
                 const R cu = R(L::cx[k]) * ux + R(L::cy[k]) * uy + R(L::cz[k]) * uz;
                 const R cv = R(L::cx[k]) * vx + R(L::cy[k]) * vy + R(L::cz[k]) * vz;
-                const R Pu = eq_poly(w, cu, uu);
-                const R Pv = eq_poly(w, cv, vv);
+                // eq:feq: w (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u^2)
+                const R Pu = w * (base_u + cu * (R(3) + R(4.5) * cu));
+                const R Pv = w * (base_v + cv * (R(3) + R(4.5) * cv));
                 // N' = N + (Neq(u) - N)/tau + Neq(v) - Neq(u)      (eq:lbe, eq:edm)
                 const R nn = rho * Pv + keepN * (pk_n[k] - rho * Pu);
                 // g' = g + (geq(u) - g)/tau_E + g dE/E [+ geq(v) - geq(u)]   (eq:gk, section 4)
@@ -383,23 +438,23 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
                 const S nn_s = S(nn), gn_s = S(gn);
                 sumN += double(nn_s);
                 sumG += double(gn_s);
-                dst[(long long)k * g.plane + own] = nn_s;
-                dst[(long long)(Q + k) * g.plane + own] = gn_s;
+                io.store(k, own, nn_s);
+                io.store(Q + k, own, gn_s);
             }
-            dst[own] = S(rho_d - sumN);
-            dst[(long long)Q * g.plane + own] = S(E_d + double(dE) - sumG);
+            io.store(0, own, S(rho_d - sumN));
+            io.store(Q, own, S(E_d + double(dE) - sumG));
         }
         __syncthreads();
     }
 }
 
-template <int Q, class S, class R, int TX, int TY, bool PIPE>
+template <int Q, class S, class R, int TX, int TY, bool PIPE, bool BUF>
 __global__ void __launch_bounds__(TX* TY)
 k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const Phys ph,
        const StepAux aux)
 {
-    step_tile<Q, S, R, TX, TY, PIPE>(src, dst, g, ph, aux,
-                                     xcd_logical_block(blockIdx.x, gridDim.x));
+    step_tile<Q, S, R, TX, TY, PIPE, BUF>(src, dst, g, ph, aux,
+                                          xcd_logical_block(blockIdx.x, gridDim.x));
 }
 
 }  // namespace lbm
