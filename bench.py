@@ -12,6 +12,9 @@ Prints ONE JSON line:
               x 4 B = 304 B per node update, divided by the measured launch duration, against
               the 8 TB/s peak; 'traffic' is the HBM traffic per launch measured by rocprofv3
               counters (profiles/), or null when not measured for the current kernel source;
+  serving   - continuous batching of a stream of uneven requests through the device pool:
+              p50/p99 time-to-result under a Poisson stream at 0.8x the burst capacity,
+              aggregate MLUPS batched and one at a time (skip with --no-serving);
   cpu_baseline - the FP64 CPU oracle timed on the host cores on a bounded sample (a few steps
               of the same 128^3 workload).
 
@@ -109,6 +112,50 @@ def copy_probe(gib=1.0, reps=5):
                       "launches": reps}), flush=True)
 
 
+def serving_bench(count=48, steps_range=(100, 1000), budget_gib=4.0, max_slots=64,
+                  steps_per_run=20, load=0.8):
+    """Continuous-batching serving of a stream of uneven D3Q19 FP32 requests (edges 32..128,
+    droplet or slab, T/Tc in [0.70, 0.95], +-1% noise; step counts scaled down from the
+    500..5000 of the full request mix so the run stays short).  Three passes over the same
+    request list: a burst (all arrive at t = 0) measures the batched capacity; a Poisson stream
+    offered at `load` x that capacity gives p50/p99 time-to-result; the same requests one after
+    another with a single simulation each give the one-at-a-time rate."""
+    from paper_1705_10045_amd import inputs as I
+    from paper_1705_10045_amd import lbm
+    from paper_1705_10045_amd import serve
+    import numpy as np
+    reqs = I.serving_requests(count=count, steps_range=steps_range)
+    work = np.array([r["edge"] ** 3 * r["steps"] for r in reqs], dtype=np.float64)
+    budget = int(budget_gib * (1 << 30))
+
+    def run(arrivals):
+        with lbm.Pool(budget, max_slots=max_slots, steps_per_run=steps_per_run) as pool:
+            return serve.serve(reqs, arrivals, serve.PoolExecutor(pool))
+
+    print("serving: burst of %d requests" % count, file=sys.stderr, flush=True)
+    burst = run(np.zeros(count))
+    rate = load * burst["aggregate_mlups"] * 1e6 / work.mean()
+    print("serving: Poisson stream at %.2f requests/s" % rate, file=sys.stderr, flush=True)
+    stream = run(serve.poisson_arrivals(count, rate))
+    print("serving: one at a time", file=sys.stderr, flush=True)
+    single = serve.one_at_a_time(reqs)
+
+    def brief(r):
+        return {"p50_s": round(r["p50_s"], 4), "p99_s": round(r["p99_s"], 4),
+                "aggregate_mlups": round(r["aggregate_mlups"], 1), "wall_s": round(r["wall_s"], 3),
+                "completed": r["completed"], "failed": r["failed"],
+                "peak_in_flight": r["peak_in_flight"], "replays": r["replays"]}
+    return {"requests": count, "edges": sorted(set(r["edge"] for r in reqs)),
+            "steps_range": list(steps_range), "node_updates": int(work.sum()),
+            "hbm_budget_gib": budget_gib, "max_slots": max_slots,
+            "steps_per_replay": steps_per_run,
+            "burst": brief(burst),
+            "poisson": dict(brief(stream), offered_load=load,
+                            rate_per_s=round(rate, 3)),
+            "one_at_a_time_mlups": round(single["aggregate_mlups"], 1),
+            "one_at_a_time_wall_s": round(single["wall_s"], 3)}
+
+
 def sweep(sim, stream, n, storage, chunks=(4, 8, 16, 32), steps=40):
     """Time each launch variant from the same checkpointed state; every variant must reproduce
     the same fields bit for bit."""
@@ -159,6 +206,11 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="time every tile variant x z-chunk of the step kernel (tuning)")
+    ap.add_argument("--serving", action="store_true",
+                    help="only the serving measurement (burst, Poisson stream, one at a time)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving measurement in the default line")
+    ap.add_argument("--serving-requests", type=int, default=48)
     ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--chunk", type=int, default=0)
     args = ap.parse_args()
@@ -176,6 +228,11 @@ def main():
     from paper_1705_10045_amd import lbm
     if not os.path.exists(lib_build.LIB):
         lib_build.build()
+
+    if args.serving:
+        print(json.dumps({"metric": "serving time-to-result (p50/p99) and aggregate MLUPS",
+                          "serving": serving_bench(count=args.serving_requests)}), flush=True)
+        return
 
     case, storage, config = workload(args.workload)
     n = case["rho0"].size
@@ -226,6 +283,8 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_alg},
         "totals_fp64": [float(x) for x in totals],
     }
+    if not args.no_serving:
+        out["serving"] = serving_bench(count=args.serving_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)

@@ -231,8 +231,8 @@ lbm_status validate_fields(const lbm_params& p, const double* rho0, const double
 void choose_geometry(lbm_sim* s, int chunk_request)
 {
     const lbm_params& p = s->p;
-    int tx, ty;
-    step_tile(p.lattice, p.storage_bytes, s->variant, tx, ty);
+    int tx, ty, per_cu;
+    step_tile(p.lattice, p.storage_bytes, s->variant, tx, ty, per_cu);
     StepGeom& g = s->geom;
     g.nx = p.nx; g.ny = p.ny; g.nz = p.nz;
     g.plane = s->plane;
@@ -240,10 +240,11 @@ void choose_geometry(lbm_sim* s, int chunk_request)
     g.nty = (p.ny + ty - 1) / ty;
     int chunk = p.nz;
     if (p.lattice == 19) {
-        // about two workgroups per compute unit (512), z chunks of at most 32 planes: longer
-        // chunks re-read fewer halo planes, more workgroups balance the load
+        // about as many workgroups as the 256 compute units hold at once, z chunks of at most
+        // 32 planes: longer chunks re-read fewer halo planes, more workgroups balance the load
         const long long cols = (long long)g.ntx * g.nty;
-        long long want = (512 + cols - 1) / cols;
+        const long long target = 256LL * per_cu;
+        long long want = (target + cols - 1) / cols;
         const long long maxc = p.nz / 4 > 0 ? p.nz / 4 : 1;
         if (want > maxc) want = maxc;
         if (want < 1) want = 1;

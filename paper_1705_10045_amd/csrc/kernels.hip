@@ -185,45 +185,61 @@ inline bool fits_buffer(const StepGeom& g, int Q, int storage_bytes)
     return (unsigned long long)g.plane * 2ull * Q * storage_bytes < (1ull << 32);
 }
 
-template <int Q, class S, class R, int TX, int TY, bool PIPE>
+template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool CEARLY, bool BUF,
+          int NMODE>
+hipError_t launch_one(const void* src, void* dst, const StepGeom& g, const Phys& ph,
+                      const StepAux& aux, hipStream_t st)
+{
+    const unsigned nblk = (unsigned)(g.ntx * g.nty * g.nchunks);
+    hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, CEARLY>), dim3(nblk),
+                       dim3(NTH), 0, st, (const S*)src, (S*)dst, g, ph, aux);
+    return hipGetLastError();
+}
+
+// Picks the instantiation for the run-time facts: buffer addressing if the state allows it,
+// and the tau = 1 collision (no re-read of N_k) when 1/tau is exactly 1.
+template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool CEARLY>
 hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Phys& ph,
                          const StepAux& aux, hipStream_t st)
 {
-    const unsigned nblk = (unsigned)(g.ntx * g.nty * g.nchunks);
+    const bool tau1 = ph.omega == 1.0;
     if constexpr (sizeof(S) == 4) {
         if (fits_buffer(g, Q, 4)) {
-            hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, PIPE, true>), dim3(nblk), dim3(TX * TY), 0,
-                               st, (const S*)src, (S*)dst, g, ph, aux);
-            return hipGetLastError();
+            return tau1 ? launch_one<Q, S, R, TX, TY, NTH, PIPE, CEARLY, true, kTauOne>(src, dst, g, ph, aux, st)
+                        : launch_one<Q, S, R, TX, TY, NTH, PIPE, CEARLY, true, kTauAny>(src, dst, g, ph, aux, st);
         }
     }
-    hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, PIPE, false>), dim3(nblk), dim3(TX * TY), 0, st,
-                       (const S*)src, (S*)dst, g, ph, aux);
-    return hipGetLastError();
+    return tau1 ? launch_one<Q, S, R, TX, TY, NTH, PIPE, CEARLY, false, kTauOne>(src, dst, g, ph, aux, st)
+                : launch_one<Q, S, R, TX, TY, NTH, PIPE, CEARLY, false, kTauAny>(src, dst, g, ph, aux, st);
 }
 
 }  // namespace
 
 // Launch shapes of the fused step.  Variant 0 is the default per (lattice, storage); the others
-// exist for FP32 D3Q19 (the bandwidth-critical path) and are selected for tuning.  Tile shape
-// and prefetching do not change the per-node arithmetic, so every variant gives
-// bitwise-identical results.
-struct TileShape { int tx, ty; bool pipe; };
+// exist for FP32 D3Q19 (the bandwidth-critical path) and are selected for tuning.  Tile shape,
+// thread count and the order of the loads do not change the per-node arithmetic, so every
+// variant gives bitwise-identical results.
+// `per_cu` is the number of workgroups of the variant resident per compute unit (set by its
+// registers and LDS); the automatic z chunk aims at about 256 * per_cu workgroups.
+struct TileShape { int tx, ty, threads; bool pipe, cearly; int per_cu; };
 static const TileShape kVariants19f[] = {
-    {32, 8, false}, {32, 8, true}, {64, 4, true}, {32, 16, true}, {16, 16, true}};
+    {32, 16, 768, false, false, 1}, {32, 16, 768, false, true, 1}, {32, 8, 512, false, false, 2},
+    {32, 8, 256, false, false, 3},  {32, 8, 512, true, true, 1},   {32, 24, 1024, false, false, 1}};
 constexpr int kNumVariants19f = sizeof(kVariants19f) / sizeof(kVariants19f[0]);
 
 int step_variants(int Q, int storage_bytes) { return (Q == 19 && storage_bytes == 4) ? kNumVariants19f : 1; }
 
-void step_tile(int Q, int storage_bytes, int variant, int& tx, int& ty)
+void step_tile(int Q, int storage_bytes, int variant, int& tx, int& ty, int& per_cu)
 {
     if (Q == 19 && storage_bytes == 4 && variant >= 0 && variant < kNumVariants19f) {
         tx = kVariants19f[variant].tx;
         ty = kVariants19f[variant].ty;
+        per_cu = kVariants19f[variant].per_cu;
         return;
     }
     tx = 32;
     ty = (Q == 19 && storage_bytes == 8) ? 4 : 8;
+    per_cu = 2;
 }
 
 hipError_t launch_step(int Q, int storage_bytes, int variant, const void* src, void* dst,
@@ -231,17 +247,18 @@ hipError_t launch_step(int Q, int storage_bytes, int variant, const void* src, v
 {
     if (Q == 19 && storage_bytes == 4) {
         switch (variant) {
-        case 0: return launch_step_t<19, float, float, 32, 8, false>(src, dst, g, ph, aux, st);
-        case 1: return launch_step_t<19, float, float, 32, 8, true>(src, dst, g, ph, aux, st);
-        case 2: return launch_step_t<19, float, float, 64, 4, true>(src, dst, g, ph, aux, st);
-        case 3: return launch_step_t<19, float, float, 32, 16, true>(src, dst, g, ph, aux, st);
-        case 4: return launch_step_t<19, float, float, 16, 16, true>(src, dst, g, ph, aux, st);
+        case 0: return launch_step_t<19, float, float, 32, 16, 768, false, false>(src, dst, g, ph, aux, st);
+        case 1: return launch_step_t<19, float, float, 32, 16, 768, false, true>(src, dst, g, ph, aux, st);
+        case 2: return launch_step_t<19, float, float, 32, 8, 512, false, false>(src, dst, g, ph, aux, st);
+        case 3: return launch_step_t<19, float, float, 32, 8, 256, false, false>(src, dst, g, ph, aux, st);
+        case 4: return launch_step_t<19, float, float, 32, 8, 512, true, true>(src, dst, g, ph, aux, st);
+        case 5: return launch_step_t<19, float, float, 32, 24, 1024, false, false>(src, dst, g, ph, aux, st);
         default: return hipErrorInvalidValue;
         }
     }
-    if (Q == 19 && storage_bytes == 8) return launch_step_t<19, double, double, 32, 4, false>(src, dst, g, ph, aux, st);
-    if (Q == 9 && storage_bytes == 4) return launch_step_t<9, float, float, 32, 8, true>(src, dst, g, ph, aux, st);
-    if (Q == 9 && storage_bytes == 8) return launch_step_t<9, double, double, 32, 8, false>(src, dst, g, ph, aux, st);
+    if (Q == 19 && storage_bytes == 8) return launch_step_t<19, double, double, 32, 4, 128, false, false>(src, dst, g, ph, aux, st);
+    if (Q == 9 && storage_bytes == 4) return launch_step_t<9, float, float, 32, 8, 256, true, false>(src, dst, g, ph, aux, st);
+    if (Q == 9 && storage_bytes == 8) return launch_step_t<9, double, double, 32, 8, 256, false, false>(src, dst, g, ph, aux, st);
     return hipErrorInvalidValue;
 }
 

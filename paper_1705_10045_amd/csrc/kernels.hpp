@@ -24,7 +24,7 @@ struct StepAux {
 };
 
 int step_variants(int Q, int storage_bytes);
-void step_tile(int Q, int storage_bytes, int variant, int& tx, int& ty);
+void step_tile(int Q, int storage_bytes, int variant, int& tx, int& ty, int& per_cu);
 hipError_t launch_step(int Q, int storage_bytes, int variant, const void* src, void* dst,
                        const StepGeom& g, const Phys& ph, const StepAux& aux, hipStream_t st);
 hipError_t launch_init(int Q, int storage_bytes, void* buf, const double* rho0, const double* u0,

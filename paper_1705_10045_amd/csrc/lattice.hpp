@@ -51,6 +51,17 @@ __host__ __device__ constexpr double weight(int k)
                             : (norm2<Q>(k) == 1 ? Lattice<Q>::w_axis : Lattice<Q>::w_diag);
 }
 
+// Index of the direction opposite to k (c_opp = -c_k).
+template <int Q>
+__host__ __device__ constexpr int opposite(int k)
+{
+    for (int j = 0; j < Q; ++j)
+        if (Lattice<Q>::cx[j] == -Lattice<Q>::cx[k] && Lattice<Q>::cy[j] == -Lattice<Q>::cy[k] &&
+            Lattice<Q>::cz[j] == -Lattice<Q>::cz[k])
+            return j;
+    return -1;
+}
+
 template <int Q>
 __host__ __device__ constexpr double force_coef(int k)
 {

@@ -28,7 +28,7 @@
 namespace lbm {
 
 constexpr int kPoolTX = 32, kPoolTY = 8;   // tile of the FP32 D3Q19 step
-constexpr int kPoolChunk = 8;              // z planes per tile: uniform tile work in the mix
+constexpr int kPoolChunk = 16;             // z planes per tile: uniform tile work in the mix
 constexpr int kPoolGrid = 2048;            // workgroups of the persistent batched launch
 constexpr int kPoolMaxEdge = 128;
 
@@ -55,7 +55,9 @@ k_pool_step(const SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ h
 {
     const int total = hdr->total_tiles;
     const int nslots = hdr->nslots;
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    // XCD-aware order: each XCD walks contiguous runs of the work list, so neighbouring tiles
+    // of one request share that XCD's L2
+    for (int t = xcd_logical_block(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
         // slot owning tile t: last slot with tile_begin <= t (binary search, workgroup-uniform)
         int lo = 0, hi = nslots - 1;
         while (lo < hi) {
@@ -76,7 +78,8 @@ k_pool_step(const SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ h
         aux.tab_s0 = s0;
         aux.tab_inv_ds = inv_ds;
         aux.err = errs + lo;
-        step_tile<19, float, float, kPoolTX, kPoolTY, true, true>(src, dst, g, ph, aux, local);
+        step_tile<19, float, float, kPoolTX, kPoolTY, kPoolTX * kPoolTY, false, true, kTauRuntime, false>(
+            src, dst, g, ph, aux, local);
     }
 }
 

@@ -30,6 +30,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "lattice.hpp"
 #include "physics.hpp"
@@ -114,9 +116,29 @@ struct PopIO<float, true> {
     }
 };
 
+// How the collision treats the density populations: with tau = 1 the BGK term of N' no longer
+// depends on N_k (N' = Neq(rho, u + du) exactly), so they need not be re-read.
+enum NMode : int {
+    kTauOne = 0,     // caller guarantees tau = 1
+    kTauAny = 1,     // always re-read N_k
+    kTauRuntime = 2  // decide per call from the parameters
+};
+
 // One workgroup's share of a step: tile `lb` (x fastest, then y, then z chunk) of the box
-// described by g.  Must be called by all TX*TY threads of the workgroup.
-template <int Q, class S, class R, int TX, int TY, bool PIPE, bool BUF>
+// described by g.  Must be called by all NTH threads of the workgroup (NTH >= TX*TY).
+//
+// Work of a thread: the collision of tile node `tid` (tid < TX*TY); moment slot `tid` of the
+// tile + 2-halo region and, when the region has more slots than threads, one of the remaining
+// slots if the thread has no collision work (else slots are dealt round-robin); force slot
+// `tid` (+ NTH ...) of the tile + 1-halo region.  Slots are numbered interior first, so a
+// thread's first moment and force slots are its own collision node and the own node's
+// moments and force stay in registers between the stages.
+//
+// PIPE: the pulls of the next plane's first moment slot are issued right after the current
+// plane's sums.  CEARLY: the collision's own pulls are issued at the top of the iteration,
+// together with the moment-stage pulls, so both memory round trips overlap.
+template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool BUF, int NMODE,
+          bool CEARLY>
 __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restrict__ dst,
                                           const StepGeom& g, const Phys& ph, const StepAux& aux,
                                           const int lb)
@@ -126,14 +148,18 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     using L = Lattice<Q>;
     constexpr int D = L::D;
     constexpr int ZH = (D == 3) ? 2 : 0;    // lead of the moment stage over the collision
-    constexpr int NT = TX * TY;
+    constexpr int NC = TX * TY;             // collision threads
+    static_assert(NTH >= NC && NTH % 64 == 0, "one collision node per thread");
     constexpr int EX = TX + 4, EY = TY + 4, NE = EX * EY;   // moments: tile + 2-halo
     constexpr int FX = TX + 2, FY = TY + 2, NF = FX * FY;   // force/u*: tile + 1-halo
     constexpr int RING = (D == 3) ? 4 : 1;  // planes of Phi, rho, T held (zc-1 .. zc+2)
     constexpr int JR = (D == 3) ? 2 : 1;    // planes of j held (zf, zf+1)
     constexpr int UR = (D == 3) ? 3 : 1;    // planes of u* held (zc-1 .. zc+1)
-    constexpr int ME = (NE + NT - 1) / NT;
-    constexpr int MF = (NF + NT - 1) / NT;
+    // moment slots beyond the first NTH go to threads without collision work when they fit
+    constexpr int EXTRA = NE > NTH ? NE - NTH : 0;
+    constexpr bool SPARE = EXTRA > 0 && EXTRA <= NTH - NC;
+    constexpr int ME = SPARE ? 2 : (NE + NTH - 1) / NTH;
+    constexpr int MF = (NF + NTH - 1) / NTH;
 
     __shared__ double sPhi[RING][NE];
     __shared__ R sRho[RING][NE];
@@ -154,12 +180,13 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     const int nxy = g.nx * g.ny;
 
     // moment-stage slots of this thread: LDS index and wrapped x / y*nx of (node - c) for
-    // c = +1, 0, -1 (index 1 - c)
+    // c = +1, 0, -1 (index 1 - c); m_e < 0 marks no slot
     int m_e[ME];
     int m_x[ME][3], m_y[ME][3];
 #pragma unroll
     for (int r = 0; r < ME; ++r) {
-        const int s = tid + r * NT;
+        int s = tid + r * NTH;
+        if constexpr (SPARE) s = r == 0 ? tid : (tid >= NC ? NTH + (tid - NC) : NE);
         m_e[r] = -1;
         m_x[r][0] = m_x[r][1] = m_x[r][2] = 0;
         m_y[r][0] = m_y[r][1] = m_y[r][2] = 0;
@@ -180,7 +207,7 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     int f_e[MF], f_f[MF];
 #pragma unroll
     for (int r = 0; r < MF; ++r) {
-        const int s = tid + r * NT;
+        const int s = tid + r * NTH;
         f_f[r] = -1;
         f_e[r] = 0;
         if (s < NF) {
@@ -193,7 +220,7 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     // this thread's own node (slot 0 of every stage)
     const int otx = tid % TX, oty = tid / TX;
     const int ox = x0 + otx, oy = y0 + oty;
-    const bool own_in_xy = ox < g.nx && oy < g.ny;
+    const bool own_in_xy = tid < NC && ox < g.nx && oy < g.ny;
     const int oe = (otx + 2) + EX * (oty + 2);
     const int of = (otx + 1) + FX * (oty + 1);
     const int xs[3] = {m_x[0][0], m_x[0][1], m_x[0][2]};   // slot 0 is the own node
@@ -201,12 +228,11 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
 
     const R omega_E = R(ph.omega_E);
     const R keepN = R(1.0 - ph.omega), keepG = R(1.0 - ph.omega_E);
-    // with tau = 1 the BGK term of N' no longer depends on N_k (N' = Neq(rho, v)): the
-    // density populations are then not re-read (keepN * (0 - rho Pu) adds an exact zero)
-    const bool needN = keepN != R(0);
     const R cond_half = R(ph.cond_half);
     const unsigned flags = ph.flags;
     const bool pseudo = (flags & kPseudo) != 0;
+    // whether the collision re-reads the density populations (not needed with tau = 1)
+    const bool needN = NMODE == kTauAny || (NMODE == kTauRuntime && keepN != R(0));
 
     // register ring of the own node's moments: [0] newest plane ... [ZH] plane being collided
     double o_rho[ZH + 1], o_E[ZH + 1], o_p[ZH + 1];
@@ -218,9 +244,8 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         o_E[q] = 1.0; o_T[q] = R(1); o_p[q] = 0.0;
     }
 
-    // populations of the moment-stage slots for one plane
-    S pn[ME][Q], pe[ME][Q];
-    auto load_plane = [&](int zm) {
+    // pulls of moment slot r at plane zm: N_k(x, t) = N*_k(x - c_k), g likewise
+    auto load_slot = [&](int zm, int r, S (&pn)[Q], S (&pe)[Q]) {
         int zoff[3];
         if constexpr (D == 3) {
             zoff[0] = wrap_index(zm - 1, g.nz) * nxy;
@@ -229,78 +254,220 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         } else {
             zoff[0] = zoff[1] = zoff[2] = 0;
         }
+        // the nine (y, z) rows the pulls of this slot read from
+        int row[3][3];
 #pragma unroll
-        for (int r = 0; r < ME; ++r) {
-            if (m_e[r] < 0) continue;
-            // the nine (y, z) rows the pulls of this slot read from
-            int row[3][3];
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) row[a][b] = zoff[a] + m_y[r][b];
 #pragma unroll
-                for (int b = 0; b < 3; ++b) row[a][b] = zoff[a] + m_y[r][b];
-#pragma unroll
-            for (int k = 0; k < Q; ++k) {
-                const int off = row[1 - L::cz[k]][1 - L::cy[k]] + m_x[r][1 - L::cx[k]];
-                pn[r][k] = io.load(k, off);
-                pe[r][k] = io.load(Q + k, off);
-            }
+        for (int k = 0; k < Q; ++k) {
+            const int off = row[1 - L::cz[k]][1 - L::cy[k]] + m_x[r][1 - L::cx[k]];
+            pn[k] = io.load(k, off);
+            pe[k] = io.load(Q + k, off);
         }
     };
 
-    const int niter = (z1 - z0) + 2 * ZH;
-    if constexpr (PIPE) load_plane(z0 - ZH);
-    for (int it = 0; it < niter; ++it) {
-        const int zm = z0 - ZH + it;
-        const int sm = ring(zm);
-        const int sj = jring(zm);
-        if constexpr (!PIPE) load_plane(zm);
+    // moments, EOS and Phi of moment slot r (plane in ring slots sm, sj)
+    auto moments = [&](int r, const S (&pn)[Q], const S (&pe)[Q], int sm, int sj) {
+        // moments summed in FP64 (exact for FP32 populations up to the final rounding)
+        double dr = 0.0, djx = 0.0, djy = 0.0, djz = 0.0, dE = 0.0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const double n = double(pn[k]);
+            dr += n;
+            dE += double(pe[k]);
+            if (L::cx[k] == 1) djx += n; else if (L::cx[k] == -1) djx -= n;
+            if (L::cy[k] == 1) djy += n; else if (L::cy[k] == -1) djy -= n;
+            if (L::cz[k] == 1) djz += n; else if (L::cz[k] == -1) djz -= n;
+        }
+        const double dT = dE / (dr * ph.c_v);
+        const double Te = (flags & kBaro) ? ph.T0_baro : dT;
+        const double p = vdw_pressure(dr, Te, ph);
+        double phi2 = dr * kTheta - p;
+        const bool ok = phi2 > 0.0 && dr * ph.inv_rho_c < 3.0 && dr > 0.0 && dE == dE &&
+                        dE < 1e30;
+        if (!ok) {
+            atomicOr(aux.err, 1);
+            phi2 = 0.0;
+        }
+        const R rho = R(dr), T = R(dT);
+        const int e = m_e[r];
+        sPhi[sm][e] = sqrt(phi2);
+        sRho[sm][e] = rho;
+        sT[sm][e] = T;
+        sJ[0][sj][e] = R(djx);
+        sJ[1][sj][e] = R(djy);
+        sJ[2][sj][e] = R(djz);
+        if (r == 0) {
+#pragma unroll
+            for (int q = ZH; q > 0; --q) {
+                o_rho[q] = o_rho[q - 1]; o_jx[q] = o_jx[q - 1]; o_jy[q] = o_jy[q - 1];
+                o_jz[q] = o_jz[q - 1]; o_E[q] = o_E[q - 1]; o_T[q] = o_T[q - 1];
+                o_p[q] = o_p[q - 1];
+            }
+            o_rho[0] = dr; o_jx[0] = R(djx); o_jy[0] = R(djy); o_jz[0] = R(djz);
+            o_E[0] = dE; o_T[0] = T; o_p[0] = p;
+        }
+    };
 
-        // ---------------- M: moments, EOS, Phi on the tile + 2-halo of plane zm
+    // the own node's pulls for the collision at plane zc (moving directions; the rest ones
+    // follow from the balances)
+    R pk_n[Q], pk_e[Q];
+    auto load_own = [&](int zc, auto with_n) {
+        constexpr bool WN = decltype(with_n)::value;
+        const int zoc = wrap_index(zc, g.nz) * nxy;
+        int zpull[3] = {zoc, zoc, zoc};
+        if constexpr (D == 3) {
+            zpull[0] = wrap_index(zc - 1, g.nz) * nxy;
+            zpull[2] = wrap_index(zc + 1, g.nz) * nxy;
+        }
+        int row[3][3];
 #pragma unroll
-        for (int r = 0; r < ME; ++r) {
-            if (m_e[r] < 0) continue;
-            // moments summed in FP64 (exact for FP32 populations up to the final rounding)
-            double dr = 0.0, djx = 0.0, djy = 0.0, djz = 0.0, dE = 0.0;
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int k = 0; k < Q; ++k) {
-                const double n = double(pn[r][k]);
-                dr += n;
-                dE += double(pe[r][k]);
-                if (L::cx[k] == 1) djx += n; else if (L::cx[k] == -1) djx -= n;
-                if (L::cy[k] == 1) djy += n; else if (L::cy[k] == -1) djy -= n;
-                if (L::cz[k] == 1) djz += n; else if (L::cz[k] == -1) djz -= n;
-            }
-            const double dT = dE / (dr * ph.c_v);
-            const double Te = (flags & kBaro) ? ph.T0_baro : dT;
-            const double p = vdw_pressure(dr, Te, ph);
-            double phi2 = dr * kTheta - p;
-            const bool ok = phi2 > 0.0 && dr * ph.inv_rho_c < 3.0 && dr > 0.0 && dE == dE &&
-                            dE < 1e30;
-            if (!ok) {
-                atomicOr(aux.err, 1);
-                phi2 = 0.0;
-            }
-            const R rho = R(dr), T = R(dT);
-            const int e = m_e[r];
-            sPhi[sm][e] = sqrt(phi2);
-            sRho[sm][e] = rho;
-            sT[sm][e] = T;
-            sJ[0][sj][e] = R(djx);
-            sJ[1][sj][e] = R(djy);
-            sJ[2][sj][e] = R(djz);
-            if (r == 0) {
+            for (int b = 0; b < 3; ++b) row[a][b] = zpull[a] + ys[b];
 #pragma unroll
-                for (int q = ZH; q > 0; --q) {
-                    o_rho[q] = o_rho[q - 1]; o_jx[q] = o_jx[q - 1]; o_jy[q] = o_jy[q - 1];
-                    o_jz[q] = o_jz[q - 1]; o_E[q] = o_E[q - 1]; o_T[q] = o_T[q - 1];
-                    o_p[q] = o_p[q - 1];
-                }
-                o_rho[0] = dr; o_jx[0] = R(djx); o_jy[0] = R(djy); o_jz[0] = R(djz);
-                o_E[0] = dE; o_T[0] = T; o_p[0] = p;
+        for (int k = 1; k < Q; ++k) {
+            const int off = row[1 - L::cz[k]][1 - L::cy[k]] + xs[1 - L::cx[k]];
+            pk_e[k] = R(io.load(Q + k, off));
+            pk_n[k] = WN ? R(io.load(k, off)) : R(0);
+        }
+    };
+    auto load_own_any = [&](int zc) {
+        if constexpr (NMODE == kTauOne) {
+            load_own(zc, std::false_type{});
+        } else if constexpr (NMODE == kTauAny) {
+            load_own(zc, std::true_type{});
+        } else {
+            if (needN) load_own(zc, std::true_type{});
+            else load_own(zc, std::false_type{});
+        }
+    };
+
+    // energy source and both collisions of the own node at plane zc; stores the result
+    auto collide = [&](int zc, auto with_n) {
+        constexpr bool WN = decltype(with_n)::value;
+        const int sc = ring(zc), scm = ring(zc - 1), scp = ring(zc + 1);
+        const int suc = uring(zc), sucm = uring(zc - 1), sucp = uring(zc + 1);
+        const int own = wrap_index(zc, g.nz) * nxy + oy * g.nx + ox;
+
+        const double rho_d = o_rho[ZH], E_d = o_E[ZH];
+        const R rho = R(rho_d), E = R(E_d), T = o_T[ZH];
+        const double p = o_p[ZH];
+        const R* Fo = (ZH > 0) ? fprev : fcur;
+        const R inv_rho = R(1) / rho;
+        const R ux = o_jx[ZH] * inv_rho, uy = o_jy[ZH] * inv_rho, uz = o_jz[ZH] * inv_rho;
+        const R dux = Fo[0] * inv_rho, duy = Fo[1] * inv_rho, duz = Fo[2] * inv_rho;
+
+        // div u* by central differences on each axis (section 6.2)
+        R div = R(0.5) * (sU[0][suc][of + 1] - sU[0][suc][of - 1]) +
+                R(0.5) * (sU[1][suc][of + FX] - sU[1][suc][of - FX]);
+        if constexpr (D == 3) div += R(0.5) * (sU[2][sucp][of] - sU[2][sucm][of]);
+
+        R dE = R(0);
+        if (flags & kWork) dE -= R(p) * div;
+        if (flags & kConduction) {
+            const R Tc = sT[sc][oe];
+            R acc = (rho + sRho[sc][oe + 1]) * (sT[sc][oe + 1] - Tc) -
+                    (rho + sRho[sc][oe - 1]) * (Tc - sT[sc][oe - 1]) +
+                    (rho + sRho[sc][oe + EX]) * (sT[sc][oe + EX] - Tc) -
+                    (rho + sRho[sc][oe - EX]) * (Tc - sT[sc][oe - EX]);
+            if constexpr (D == 3)
+                acc += (rho + sRho[scp][oe]) * (sT[scp][oe] - Tc) -
+                       (rho + sRho[scm][oe]) * (Tc - sT[scm][oe]);
+            dE += cond_half * acc;
+        }
+        if (flags & kLatent) {
+            const double Te = (flags & kBaro) ? ph.T0_baro : double(T);
+            double r1, r2;
+            if (band_limits(Te * ph.inv_T_c, aux.maxwell, aux.tab_s0, aux.tab_inv_ds, ph.rho_c,
+                            r1, r2)) {
+                const double rd = double(rho);
+                if (rd > r1 && rd < r2) dE -= R(ph.rhoQ / (r2 - r1) * rd * double(div));
             }
         }
-        if constexpr (PIPE) {
-            if (it + 1 < niter) load_plane(zm + 1);
+
+        const R vx = ux + dux, vy = uy + duy, vz = uz + duz;
+        const R uu = ux * ux + uy * uy + uz * uz;
+        const R vv = vx * vx + vy * vy + vz * vz;
+        const R base_u = R(1) - R(1.5) * uu, base_v = R(1) - R(1.5) * vv;
+        // Both collisions as linear combinations of the equilibrium polynomials
+        // P_k(v) = w_k (1 + 3 c.v + 4.5 (c.v)^2 - 1.5 v^2) (eq:feq):
+        //   N'_k = rho P_k(v) - keepN rho P_k(u) + keepN N_k             (eq:lbe, eq:edm)
+        //   g'_k = gV P_k(v) + gU P_k(u) + (keepG + dE/E) g_k            (eq:gk, section 4)
+        // with (gV, gU) = (E, -keepG E) with pseudoforces, (0, E/tau_E) without.
+        const R nU = -keepN * rho;
+        const R gV = pseudo ? E : R(0);
+        const R gU = pseudo ? -keepG * E : omega_E * E;
+        const R gK = keepG + dE / E;
+        // The collision conserves mass and changes the energy by exactly dE (the BGK, EDM and
+        // pseudoforce increments sum to zero; dg(1) sums to dE).  The moving directions are
+        // computed from the equilibria and the rest populations close the balances in FP64
+        // over the values actually stored, so rounding of the lattice weights cannot create
+        // mass or energy.
+        double sumN = 0.0, sumG = 0.0;
+#pragma unroll
+        for (int k = 1; k < Q; ++k) {
+            const int ko = opposite<Q>(k);
+            if (ko < k) continue;
+            // P_k and P_-k share the even part of the polynomial
+            const R w = R(weight<Q>(k));
+            const R cu = R(L::cx[k]) * ux + R(L::cy[k]) * uy + R(L::cz[k]) * uz;
+            const R cv = R(L::cx[k]) * vx + R(L::cy[k]) * vy + R(L::cz[k]) * vz;
+            const R eu = fma(R(4.5) * w, cu * cu, w * base_u), ou = R(3) * w * cu;
+            const R ev = fma(R(4.5) * w, cv * cv, w * base_v), ov = R(3) * w * cv;
+            const R Pu[2] = {eu + ou, eu - ou}, Pv[2] = {ev + ov, ev - ov};
+            const int kk[2] = {k, ko};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int q = kk[h];
+                R nn = rho * Pv[h];
+                if constexpr (WN) nn = fma(keepN, pk_n[q], fma(nU, Pu[h], nn));
+                const R gn = fma(gK, pk_e[q], fma(gU, Pu[h], gV * Pv[h]));
+                const S nn_s = S(nn), gn_s = S(gn);
+                sumN += double(nn_s);
+                sumG += double(gn_s);
+                io.store(q, own, nn_s);
+                io.store(Q + q, own, gn_s);
+            }
+        }
+        io.store(0, own, S(rho_d - sumN));
+        io.store(Q, own, S(E_d + double(dE) - sumG));
+    };
+
+    const int niter = (z1 - z0) + 2 * ZH;
+    S pn0[Q], pe0[Q];   // pulls of the first moment slot
+    if constexpr (PIPE) {
+        if (m_e[0] >= 0) load_slot(z0 - ZH, 0, pn0, pe0);
+    }
+    for (int it = 0; it < niter; ++it) {
+        const int zm = z0 - ZH + it;
+        const int zc = zm - ZH;
+        const bool collides = it >= 2 * ZH && own_in_xy;
+        const int sm = ring(zm);
+        const int sj = jring(zm);
+
+        // ---------------- M: moments, EOS, Phi on the tile + 2-halo of plane zm
+        // Loads complete in issue order, so the order of the requests is: this plane's
+        // moment pulls (unless prefetched), the collision's pulls, the next plane's prefetch.
+        // (every collision thread owns moment slot 0: the tile lies inside the region)
+        if (m_e[0] >= 0) {
+            if constexpr (!PIPE) load_slot(zm, 0, pn0, pe0);
+            if constexpr (CEARLY) {
+                if (collides) load_own_any(zc);
+            }
+            moments(0, pn0, pe0, sm, sj);
+            if constexpr (PIPE) {
+                if (it + 1 < niter) load_slot(zm + 1, 0, pn0, pe0);
+            }
+        }
+#pragma unroll
+        for (int r = 1; r < ME; ++r) {
+            if (m_e[r] < 0) continue;
+            S pn[Q], pe[Q];
+            load_slot(zm, r, pn, pe);
+            moments(r, pn, pe, sm, sj);
         }
         __syncthreads();
 
@@ -313,26 +480,28 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             for (int r = 0; r < MF; ++r) {
                 if (f_f[r] < 0) continue;
                 const int e = f_e[r];
-                // force of section 3 in FP64 (a small difference of Phi^2 values)
-                double s1x = 0, s1y = 0, s1z = 0, s2x = 0, s2y = 0, s2z = 0;
+                // force of section 3 in FP64 (a small difference of Phi^2 values):
+                // F = (1/alpha) sum_k G_k Phi_k (A Phi_k + (1 - 2A) Phi(x)) c_k, summed over
+                // pairs of opposite directions
+                const double Am = ph.A;
+                const double Bm = (1.0 - 2.0 * Am) * sPhi[sf][e];
+                double fx = 0.0, fy = 0.0, fz = 0.0;
 #pragma unroll
                 for (int k = 1; k < Q; ++k) {
-                    const int sl = L::cz[k] == 0 ? sf : (L::cz[k] == 1 ? sfp : sfm);
-                    const double phk = sPhi[sl][e + L::cx[k] + EX * L::cy[k]];
-                    const double gph = force_coef<Q>(k) * phk;
-                    const double gph2 = gph * phk;
-                    if (L::cx[k] == 1) { s1x += gph2; s2x += gph; }
-                    else if (L::cx[k] == -1) { s1x -= gph2; s2x -= gph; }
-                    if (L::cy[k] == 1) { s1y += gph2; s2y += gph; }
-                    else if (L::cy[k] == -1) { s1y -= gph2; s2y -= gph; }
-                    if (L::cz[k] == 1) { s1z += gph2; s2z += gph; }
-                    else if (L::cz[k] == -1) { s1z -= gph2; s2z -= gph; }
+                    const int ko = opposite<Q>(k);
+                    if (ko < k) continue;
+                    const int slp = L::cz[k] == 0 ? sf : (L::cz[k] == 1 ? sfp : sfm);
+                    const int slm = L::cz[k] == 0 ? sf : (L::cz[k] == 1 ? sfm : sfp);
+                    const double pp = sPhi[slp][e + L::cx[k] + EX * L::cy[k]];
+                    const double pm = sPhi[slm][e - L::cx[k] - EX * L::cy[k]];
+                    double d = pp * fma(Am, pp, Bm) - pm * fma(Am, pm, Bm);
+                    if (force_coef<Q>(k) != 1.0) d *= force_coef<Q>(k);
+                    if (L::cx[k] == 1) fx += d; else if (L::cx[k] == -1) fx -= d;
+                    if (L::cy[k] == 1) fy += d; else if (L::cy[k] == -1) fy -= d;
+                    if (L::cz[k] == 1) fz += d; else if (L::cz[k] == -1) fz -= d;
                 }
-                const double Am = ph.A, ia = ph.inv_alpha;
-                const double b = (1.0 - 2.0 * Am) * sPhi[sf][e];
-                const R Fx = R((Am * s1x + b * s2x) * ia);
-                const R Fy = R((Am * s1y + b * s2y) * ia);
-                const R Fz = R((Am * s1z + b * s2z) * ia);
+                const double ia = ph.inv_alpha;
+                const R Fx = R(fx * ia), Fy = R(fy * ia), Fz = R(fz * ia);
                 const R inv_rho = R(1) / sRho[sf][e];
                 const int f = f_f[r];
                 sU[0][suf][f] = (sJ[0][sjf][e] + R(0.5) * Fx) * inv_rho;
@@ -347,114 +516,29 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         __syncthreads();
 
         // ---------------- C: energy source, collisions, store for plane zc = zm - ZH
-        if (it >= 2 * ZH && own_in_xy) {
-            const int zc = zm - ZH;
-            const int sc = ring(zc), scm = ring(zc - 1), scp = ring(zc + 1);
-            const int suc = uring(zc), sucm = uring(zc - 1), sucp = uring(zc + 1);
-            const int zoc = wrap_index(zc, g.nz) * nxy;
-            const int zpull[3] = {wrap_index(zc - 1, g.nz) * nxy, zoc,
-                                  wrap_index(zc + 1, g.nz) * nxy};
-            const int own = zoc + oy * g.nx + ox;
-
-            // populations of the own node (moving directions; the rest ones follow from the
-            // balances below)
-            R pk_n[Q], pk_e[Q];
-            pk_n[0] = pk_e[0] = R(0);
-            {
-                int row[3][3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) row[a][b] = (D == 3 ? zpull[a] : zoc) + ys[b];
-#pragma unroll
-                for (int k = 1; k < Q; ++k) {
-                    const int off = row[1 - L::cz[k]][1 - L::cy[k]] + xs[1 - L::cx[k]];
-                    pk_e[k] = R(io.load(Q + k, off));
-                    pk_n[k] = needN ? R(io.load(k, off)) : R(0);
-                }
+        if (collides) {
+            if constexpr (!CEARLY) load_own_any(zc);
+            if constexpr (NMODE == kTauOne) {
+                collide(zc, std::false_type{});
+            } else if constexpr (NMODE == kTauAny) {
+                collide(zc, std::true_type{});
+            } else {
+                if (needN) collide(zc, std::true_type{});
+                else collide(zc, std::false_type{});
             }
-
-            const double rho_d = o_rho[ZH], E_d = o_E[ZH];
-            const R rho = R(rho_d), E = R(E_d), T = o_T[ZH];
-            const double p = o_p[ZH];
-            const R* Fo = (ZH > 0) ? fprev : fcur;
-            const R inv_rho = R(1) / rho;
-            const R ux = o_jx[ZH] * inv_rho, uy = o_jy[ZH] * inv_rho, uz = o_jz[ZH] * inv_rho;
-            const R dux = Fo[0] * inv_rho, duy = Fo[1] * inv_rho, duz = Fo[2] * inv_rho;
-
-            // div u* by central differences on each axis (section 6.2)
-            R div = R(0.5) * (sU[0][suc][of + 1] - sU[0][suc][of - 1]) +
-                    R(0.5) * (sU[1][suc][of + FX] - sU[1][suc][of - FX]);
-            if constexpr (D == 3) div += R(0.5) * (sU[2][sucp][of] - sU[2][sucm][of]);
-
-            R dE = R(0);
-            if (flags & kWork) dE -= R(p) * div;
-            if (flags & kConduction) {
-                const R Tc = sT[sc][oe];
-                R acc = (rho + sRho[sc][oe + 1]) * (sT[sc][oe + 1] - Tc) -
-                        (rho + sRho[sc][oe - 1]) * (Tc - sT[sc][oe - 1]) +
-                        (rho + sRho[sc][oe + EX]) * (sT[sc][oe + EX] - Tc) -
-                        (rho + sRho[sc][oe - EX]) * (Tc - sT[sc][oe - EX]);
-                if constexpr (D == 3)
-                    acc += (rho + sRho[scp][oe]) * (sT[scp][oe] - Tc) -
-                           (rho + sRho[scm][oe]) * (Tc - sT[scm][oe]);
-                dE += cond_half * acc;
-            }
-            if (flags & kLatent) {
-                const double Te = (flags & kBaro) ? ph.T0_baro : double(T);
-                double r1, r2;
-                if (band_limits(Te * ph.inv_T_c, aux.maxwell, aux.tab_s0, aux.tab_inv_ds,
-                                ph.rho_c, r1, r2)) {
-                    const double rd = double(rho);
-                    if (rd > r1 && rd < r2) dE -= R(ph.rhoQ / (r2 - r1) * rd * double(div));
-                }
-            }
-            const R dEoE = dE / E;
-
-            const R vx = ux + dux, vy = uy + duy, vz = uz + duz;
-            const R uu = ux * ux + uy * uy + uz * uz;
-            const R vv = vx * vx + vy * vy + vz * vz;
-            // The collision conserves mass and changes the energy by exactly dE (the BGK,
-            // EDM and pseudoforce increments sum to zero; dg(1) sums to dE).  The moving
-            // directions are computed from the equilibria and the rest populations close the
-            // balances in FP64 over the values actually stored, so rounding of the lattice
-            // weights cannot create mass or energy.
-            double sumN = 0.0, sumG = 0.0;
-            const R base_u = R(1) - R(1.5) * uu, base_v = R(1) - R(1.5) * vv;
-#pragma unroll
-            for (int k = 1; k < Q; ++k) {
-                const R w = R(weight<Q>(k));
-                const R cu = R(L::cx[k]) * ux + R(L::cy[k]) * uy + R(L::cz[k]) * uz;
-                const R cv = R(L::cx[k]) * vx + R(L::cy[k]) * vy + R(L::cz[k]) * vz;
-                // eq:feq: w (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u^2)
-                const R Pu = w * (base_u + cu * (R(3) + R(4.5) * cu));
-                const R Pv = w * (base_v + cv * (R(3) + R(4.5) * cv));
-                // N' = N + (Neq(u) - N)/tau + Neq(v) - Neq(u)      (eq:lbe, eq:edm)
-                const R nn = rho * Pv + keepN * (pk_n[k] - rho * Pu);
-                // g' = g + (geq(u) - g)/tau_E + g dE/E [+ geq(v) - geq(u)]   (eq:gk, section 4)
-                const R e = pk_e[k];
-                const R gn = pseudo ? E * Pv + keepG * (e - E * Pu) + e * dEoE
-                                    : omega_E * E * Pu + keepG * e + e * dEoE;
-                const S nn_s = S(nn), gn_s = S(gn);
-                sumN += double(nn_s);
-                sumG += double(gn_s);
-                io.store(k, own, nn_s);
-                io.store(Q + k, own, gn_s);
-            }
-            io.store(0, own, S(rho_d - sumN));
-            io.store(Q, own, S(E_d + double(dE) - sumG));
         }
         __syncthreads();
     }
 }
 
-template <int Q, class S, class R, int TX, int TY, bool PIPE, bool BUF>
-__global__ void __launch_bounds__(TX* TY)
+template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool BUF, int NMODE,
+          bool CEARLY>
+__global__ void __launch_bounds__(NTH)
 k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const Phys ph,
        const StepAux aux)
 {
-    step_tile<Q, S, R, TX, TY, PIPE, BUF>(src, dst, g, ph, aux,
-                                          xcd_logical_block(blockIdx.x, gridDim.x));
+    step_tile<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, CEARLY>(
+        src, dst, g, ph, aux, xcd_logical_block(blockIdx.x, gridDim.x));
 }
 
 }  // namespace lbm

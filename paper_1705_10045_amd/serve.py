@@ -37,16 +37,34 @@ def percentile(values, q):
     return v[k]
 
 
+# bytes of the two FP32 D3Q19 population buffers of an L^3 request, without plane padding:
+# a lower bound of what the pool's arena must hold for it
+def request_bytes_lower_bound(edge):
+    return 2 * 2 * 19 * 4 * edge ** 3
+
+
 class PoolExecutor:
-    """Executor backed by the device pool; builds each request's initial fields on submit."""
+    """Executor backed by the device pool.  A request that cannot fit (no free slot, or fewer
+    free arena bytes than its buffers need) is declined without building its fields; a
+    request's initial fields are built once and kept until it is admitted."""
 
     def __init__(self, pool, physics=None):
         self.pool = pool
         self.physics = physics or inputs.physics()
+        self._fields = {}
 
     def submit(self, req):
-        f = inputs.request_fields(req, self.physics)
-        return self.pool.submit(f["params"], f["rho0"], f["u0"], f["T0"], req["steps"])
+        st = self.pool.stats()
+        if st["free_slots"] < 1 or (st["budget"] - st["bytes_in_use"] <
+                                    request_bytes_lower_bound(req["edge"])):
+            return None
+        f = self._fields.get(req["id"])
+        if f is None:
+            f = self._fields[req["id"]] = inputs.request_fields(req, self.physics)
+        ticket = self.pool.submit(f["params"], f["rho0"], f["u0"], f["T0"], req["steps"])
+        if ticket is not None:
+            del self._fields[req["id"]]
+        return ticket
 
     def run(self):
         self.pool.run()

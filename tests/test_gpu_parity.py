@@ -42,6 +42,30 @@ def test_d2q9_slab_full_size_100_steps(storage):
     assert max(errs.values()) < TOL[storage]
 
 
+@pytest.mark.parametrize("storage", [4, 8])
+@pytest.mark.parametrize("lattice", [9, 19])
+def test_tau_not_one(lattice, storage):
+    """tau != 1: the collision re-reads the density populations (the BGK term keeps a share
+    1 - 1/tau of N_k); tau = 1 takes the specialised collision N' = Neq(rho, u + du)."""
+    if lattice == 19:
+        case = droplet(tau=0.8)
+    else:
+        case = I.slab_2d(n=64, width=20, params=I.physics(tau=1.3))
+    errs, *_ = compare(case, 100, storage)
+    describe("tau != 1, D%dQ%d %dB" % (3 if lattice == 19 else 2, lattice, storage), errs)
+    assert max(errs.values()) < TOL[storage]
+
+
+def test_full_size_droplet_128_in_bench_launch():
+    """The 128^3 thermal droplet of the benchmark itself (radius 24, T~ 0.8, +-0.5% noise,
+    u = (0.05, 0, 0)), FP32, in the launch configuration the benchmark times, every field
+    against the oracle after 10 steps."""
+    case = I.droplet_3d(n=128, radius=24.0, Tr=0.8, noise=0.005, velocity=(0.05, 0.0, 0.0))
+    errs, *_ = compare(case, 10, 4)
+    describe("droplet 128^3 4B, 10 steps", errs)
+    assert max(errs.values()) < TOL[4]
+
+
 def test_d3q19_spinodal_fp64_100_steps():
     errs, *_ = compare(spinodal(), 100, 8)
     describe("D3Q19 spinodal 8B", errs)
@@ -204,10 +228,12 @@ def test_unstable_state_reported():
         assert e.value.status == lbm.LBM_EUNSTABLE
 
 
-def test_launch_variants_are_bitwise_identical():
-    """Every tile shape, z-chunk length and prefetch variant of the fused step computes the
-    same per-node arithmetic: results agree bit for bit (also a race check on the LDS rings)."""
-    case = droplet(shape=(21, 30, 45), radius=6.0)
+@pytest.mark.parametrize("tau", [1.0, 0.8])
+def test_launch_variants_are_bitwise_identical(tau):
+    """Every tile shape, thread count, z-chunk length and load order of the fused step computes
+    the same per-node arithmetic: results agree bit for bit (also a race check on the LDS
+    rings), for the tau = 1 collision and the general one."""
+    case = droplet(shape=(21, 30, 45), radius=6.0, tau=tau)
     ref = None
     with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"]) as s:
         ck = s.checkpoint()

@@ -52,6 +52,27 @@ def test_pool_matches_single_simulation_and_oracle():
     assert max(errs.values()) < 1e-5
 
 
+def test_pool_mixes_tau_values():
+    """One batched launch serves requests with tau = 1 and tau != 1 (the collision decides per
+    request whether to re-read N_k); each result equals its single simulation bit for bit."""
+    reqs = [(_req(11, 32, 30, "droplet", 0.8), 0.8), (_req(12, 48, 30, "slab", 0.85), 1.0)]
+    with lbm.Pool(2 * GIB, max_slots=4, steps_per_run=10) as pool:
+        tickets = []
+        for req, tau in reqs:
+            f = I.request_fields(req, I.physics(tau=tau))
+            tickets.append(pool.submit(f["params"], f["rho0"], f["u0"], f["T0"], req["steps"]))
+        for _ in range(3):
+            pool.run()
+        results = [pool.collect(t)[0] for t in tickets]
+    for (req, tau), res in zip(reqs, results):
+        f = I.request_fields(req, I.physics(tau=tau))
+        with lbm.Sim(19, f["params"], f["rho0"], f["u0"], f["T0"], storage_bytes=4) as s:
+            s.step(req["steps"])
+            single = s.moments()
+        for k in res:
+            assert np.array_equal(res[k], single[k]), (tau, k)
+
+
 def test_admission_respects_budget_and_reuses_slots():
     params = I.physics()
     f32 = I.request_fields(_req(6, 32, 30))

@@ -128,3 +128,46 @@ def test_percentile_nearest_rank():
     v = list(range(1, 101))
     assert serve.percentile(v, 50) == 50 and serve.percentile(v, 99) == 99
     assert serve.percentile([3.0], 99) == 3.0
+
+
+class _FakePool:
+    """Pool stand-in: a byte budget and slots, no device."""
+
+    def __init__(self, budget, slots):
+        self.budget, self.slots, self.used, self.next = budget, slots, 0, 1
+        self.submitted = []
+
+    def stats(self):
+        return {"active": 0, "bytes_in_use": self.used, "budget": self.budget,
+                "free_slots": self.slots}
+
+    def submit(self, params, rho0, u0, T0, steps):
+        need = serve.request_bytes_lower_bound(rho0.shape[0])
+        if self.slots < 1 or self.budget - self.used < need:
+            return None
+        self.slots -= 1
+        self.used += need
+        self.submitted.append(rho0.shape[0])
+        self.next += 1
+        return self.next - 1
+
+
+def test_pool_executor_declines_without_building_fields(monkeypatch):
+    built = []
+    real = I.request_fields
+
+    def counting(req, params=None):
+        built.append(req["id"])
+        return real(req, params)
+
+    monkeypatch.setattr(I, "request_fields", counting)
+    small = dict(id=0, edge=8, Tr=0.8, kind="droplet", steps=3, seed=I.SEED + 1, noise=0.01)
+    big = dict(id=1, edge=12, Tr=0.8, kind="slab", steps=3, seed=I.SEED + 2, noise=0.01)
+    pool = _FakePool(budget=serve.request_bytes_lower_bound(8) + 10, slots=4)
+    ex = serve.PoolExecutor(pool)
+    assert ex.submit(big) is None and built == []      # cannot fit: fields never built
+    assert ex.submit(small) == 1 and built == [0]
+    assert ex.submit(small | {"id": 2}) is None and built == [0]
+    pool.budget = 10 ** 9
+    assert ex.submit(big) == 2 and built == [0, 1]
+    assert pool.submitted == [8, 12]
