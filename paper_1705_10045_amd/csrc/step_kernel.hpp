@@ -10,18 +10,16 @@
 // the axis 1-ring, i.e. Phi on a 2-ring; conduction needs rho and T on the axis 1-ring.
 //
 // Work decomposition: a workgroup owns a TX x TY column of nodes and marches through a chunk
-// of z planes.  Per z iteration it runs three stages separated by barriers:
+// of z planes (even chunks upward, odd chunks downward).  Per z iteration it runs three
+// stages separated by barriers:
 //   M: pull 2Q populations and form rho, j, E, T, p, Phi for plane zm on the tile plus a
 //      2-node halo (LDS rings);
-//   F: force and u* for plane zm-1 on the tile plus a 1-node halo (LDS ring);
-//   C: energy source, collisions and the store for plane zm-2 on the tile.
+//   F: force and u* for the plane one behind zm on the tile plus a 1-node halo (LDS ring);
+//   C: energy source, collisions and the store for the plane two behind zm, on the tile.
 // D2Q9 runs the same code with a single plane (no z halo, no lag between the stages).
-// With PIPE the populations of the next plane's M stage are requested right after the
-// current plane's sums, so they are in flight while the F and C stages run.
 //
 // Per-node quantities of the tile's own nodes (rho, j, E, T, p, F) stay in registers between
-// the stages; populations are re-read for the collision (they were pulled two planes earlier
-// by this workgroup, so the re-read is served by the caches).
+// the stages; the moving populations of the own node are pulled again for the collision.
 //
 // Arithmetic: moments, EOS, Phi and the force in FP64 (the force is a small difference of
 // Phi^2 values); u*, the energy source and the collision in R; the rest populations close the
@@ -81,7 +79,9 @@ __device__ __forceinline__ void region_slot(int s, int& rx, int& ry)
 // Access to population (set*Q + k) at node i of the two buffers.  With BUF the state (< 4 GB)
 // is addressed through buffer resources: the node offset is a 32-bit per-lane byte offset and
 // the plane offset of the population a scalar offset, so no per-access 64-bit address
-// arithmetic is spent.  Otherwise plain global pointers.
+// arithmetic is spent.  Otherwise plain global pointers.  Stores are marked non-temporal
+// (nothing in the step reads them back), so they do not displace the halo and re-read data the
+// step still needs from L2.
 template <class S, bool BUF>
 struct PopIO;
 
@@ -92,7 +92,10 @@ struct PopIO<S, false> {
     long long plane;
     __device__ PopIO(const S* s, S* d, long long p, int) : src(s), dst(d), plane(p) {}
     __device__ __forceinline__ S load(int pk, int i) const { return src[(long long)pk * plane + i]; }
-    __device__ __forceinline__ void store(int pk, int i, S v) const { dst[(long long)pk * plane + i] = v; }
+    __device__ __forceinline__ void store(int pk, int i, S v) const
+    {
+        __builtin_nontemporal_store(v, dst + (long long)pk * plane + i);
+    }
 };
 
 template <>
@@ -106,13 +109,15 @@ struct PopIO<float, true> {
         rd = __builtin_amdgcn_make_buffer_rsrc((void*)d, (short)0, (int)bytes, 0x00020000);
         plane_bytes = (int)(p * 4);
     }
+    // cache-policy operand of the buffer instructions: bit 1 is the non-temporal hint
+    static constexpr int kNT = 2;
     __device__ __forceinline__ float load(int pk, int i) const
     {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, i * 4, pk * plane_bytes, 0));
     }
     __device__ __forceinline__ void store(int pk, int i, float v) const
     {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rd, i * 4, pk * plane_bytes, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rd, i * 4, pk * plane_bytes, kNT);
     }
 };
 
@@ -136,9 +141,13 @@ enum NMode : int {
 //
 // PIPE: the pulls of the next plane's first moment slot are issued right after the current
 // plane's sums.  CEARLY: the collision's own pulls are issued at the top of the iteration,
-// together with the moment-stage pulls, so both memory round trips overlap.
+// together with the moment-stage pulls, so both memory round trips overlap.  STASH (tau = 1
+// only): the collision does not pull its energy populations again; the moment stage already
+// pulled them for the own node, and they wait in an LDS ring of two planes (each thread keeps
+// its plane in registers until the collision has consumed the older plane of the same ring
+// slot, then moves it there).
 template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool BUF, int NMODE,
-          bool CEARLY>
+          bool CEARLY, bool STASH>
 __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restrict__ dst,
                                           const StepGeom& g, const Phys& ph, const StepAux& aux,
                                           const int lb)
@@ -166,6 +175,8 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     __shared__ R sT[RING][NE];
     __shared__ R sJ[3][JR][NE];
     __shared__ R sU[3][UR][NF];
+    constexpr bool kStash = STASH && NMODE == kTauOne && D == 3;
+    __shared__ S sG[kStash ? 2 : 1][kStash ? Q - 1 : 1][kStash ? NC : 1];
 
     auto ring = [](int z) { return (z + 4) & (RING - 1); };   // z >= -4
     auto jring = [](int z) { return (z + 4) & (JR - 1); };
@@ -335,7 +346,13 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         }
     };
     auto load_own_any = [&](int zc) {
-        if constexpr (NMODE == kTauOne) {
+        if constexpr (kStash) {
+#pragma unroll
+            for (int k = 1; k < Q; ++k) {
+                pk_e[k] = R(sG[zc & 1][k - 1][tid]);
+                pk_n[k] = R(0);
+            }
+        } else if constexpr (NMODE == kTauOne) {
             load_own(zc, std::false_type{});
         } else if constexpr (NMODE == kTauAny) {
             load_own(zc, std::true_type{});
@@ -436,14 +453,20 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         io.store(Q, own, S(E_d + double(dE) - sumG));
     };
 
+    // Chunks march upward and downward alternately, so the two chunks on either side of a
+    // chunk boundary pull its halo planes at about the same time and the second pull finds
+    // them in the caches.  The per-node arithmetic does not depend on the direction.
     const int niter = (z1 - z0) + 2 * ZH;
+    const int dir = (tiz & 1) ? -1 : 1;
+    const int zstart = dir > 0 ? z0 - ZH : z1 - 1 + ZH;
     S pn0[Q], pe0[Q];   // pulls of the first moment slot
+    S held[kStash ? Q - 1 : 1];   // own node's energy pulls of plane zm, bound for the stash
     if constexpr (PIPE) {
-        if (m_e[0] >= 0) load_slot(z0 - ZH, 0, pn0, pe0);
+        if (m_e[0] >= 0) load_slot(zstart, 0, pn0, pe0);
     }
     for (int it = 0; it < niter; ++it) {
-        const int zm = z0 - ZH + it;
-        const int zc = zm - ZH;
+        const int zm = zstart + dir * it;   // moment stage; force at zm - dir, collision at zm - 2 dir
+        const int zc = zm - dir * ZH;
         const bool collides = it >= 2 * ZH && own_in_xy;
         const int sm = ring(zm);
         const int sj = jring(zm);
@@ -458,8 +481,12 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
                 if (collides) load_own_any(zc);
             }
             moments(0, pn0, pe0, sm, sj);
+            if constexpr (kStash) {
+#pragma unroll
+                for (int k = 1; k < Q; ++k) held[k - 1] = pe0[k];
+            }
             if constexpr (PIPE) {
-                if (it + 1 < niter) load_slot(zm + 1, 0, pn0, pe0);
+                if (it + 1 < niter) load_slot(zm + dir, 0, pn0, pe0);
             }
         }
 #pragma unroll
@@ -471,9 +498,9 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         }
         __syncthreads();
 
-        // ---------------- F: force and u* on the tile + 1-halo of plane zf = zm - ZH/2
+        // ---------------- F: force and u* on the tile + 1-halo of plane zf = zm - dir ZH/2
         if (it >= ZH) {
-            const int zf = zm - ZH / 2;
+            const int zf = zm - dir * (ZH / 2);
             const int sf = ring(zf), sfm = ring(zf - 1), sfp = ring(zf + 1);
             const int sjf = jring(zf), suf = uring(zf);
 #pragma unroll
@@ -515,7 +542,7 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         }
         __syncthreads();
 
-        // ---------------- C: energy source, collisions, store for plane zc = zm - ZH
+        // ---------------- C: energy source, collisions, store for plane zc = zm - dir ZH
         if (collides) {
             if constexpr (!CEARLY) load_own_any(zc);
             if constexpr (NMODE == kTauOne) {
@@ -527,17 +554,25 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
                 else collide(zc, std::false_type{});
             }
         }
+        if constexpr (kStash) {
+            // plane zm takes the ring slot of plane zm - 2 dir, consumed just above by this
+            // same thread (every thread touches only its own column of the stash)
+            if (tid < NC) {
+#pragma unroll
+                for (int k = 1; k < Q; ++k) sG[zm & 1][k - 1][tid] = held[k - 1];
+            }
+        }
         __syncthreads();
     }
 }
 
 template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool BUF, int NMODE,
-          bool CEARLY>
+          bool CEARLY, bool STASH>
 __global__ void __launch_bounds__(NTH)
 k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const Phys ph,
        const StepAux aux)
 {
-    step_tile<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, CEARLY>(
+    step_tile<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, CEARLY, STASH>(
         src, dst, g, ph, aux, xcd_logical_block(blockIdx.x, gridDim.x));
 }
 
