@@ -156,14 +156,14 @@ def serving_bench(count=48, steps_range=(100, 1000), budget_gib=4.0, max_slots=6
             "one_at_a_time_wall_s": round(single["wall_s"], 3)}
 
 
-def sweep(sim, stream, n, storage, chunks=(4, 8, 16, 32), steps=40):
-    """Time each launch variant from the same checkpointed state; every variant must reproduce
-    the same fields bit for bit."""
+def sweep(sim, stream, n, storage, chunks=(0, 8, 16, 32), steps=40, reps=3):
+    """Time each launch variant x z-chunk (0 = automatic) from the same checkpointed state,
+    `reps` interleaved rounds, median reported; every variant must reproduce the same fields
+    bit for bit."""
     import numpy as np
     import torch
     from paper_1705_10045_amd import lbm
     ck = sim.checkpoint()
-    ref = None
     nvar = 0
     while True:
         try:
@@ -171,9 +171,14 @@ def sweep(sim, stream, n, storage, chunks=(4, 8, 16, 32), steps=40):
             nvar += 1
         except lbm.LbmError:
             break
-    for v in range(nvar):
-        for c in chunks:
-            sim.set_launch(v, c)
+    configs = [(v, c) for v in range(nvar) for c in chunks]
+    times = {cfg: [] for cfg in configs}
+    same = {}
+    info = {}
+    ref = None
+    for rep in range(reps):
+        for cfg in configs:
+            sim.set_launch(*cfg)
             sim.restore(ck)
             sim.step(5)
             start = torch.cuda.Event(enable_timing=True)
@@ -184,16 +189,21 @@ def sweep(sim, stream, n, storage, chunks=(4, 8, 16, 32), steps=40):
             end.record(stream)
             torch.cuda.synchronize()
             sim.check()
-            ms = start.elapsed_time(end) / steps
-            m = sim.moments()["rho"]
-            same = ref is None or np.array_equal(m, ref)
-            ref = m if ref is None else ref
-            info = sim.launch_info()
-            print(json.dumps({"variant": v, "tile": [info["tile_x"], info["tile_y"]], "chunk": c,
-                              "workgroups": info["workgroups"], "ms_per_step": round(ms, 4),
-                              "mlups": round(n / ms / 1e3, 1),
-                              "frac": round(BYTES_PER_UPDATE[storage] * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                              "bitwise_equal": bool(same)}), flush=True)
+            times[cfg].append(start.elapsed_time(end) / steps)
+            if rep == 0:
+                m = sim.moments()["rho"]
+                same[cfg] = ref is None or bool(np.array_equal(m, ref))
+                ref = m if ref is None else ref
+                info[cfg] = sim.launch_info()
+    for cfg in configs:
+        ms = float(np.median(times[cfg]))
+        i = info[cfg]
+        print(json.dumps({"variant": cfg[0], "tile": [i["tile_x"], i["tile_y"]], "chunk": i["chunk"],
+                          "workgroups": i["workgroups"], "ms_per_step": round(ms, 4),
+                          "ms_all": [round(t, 4) for t in times[cfg]],
+                          "mlups": round(n / ms / 1e3, 1),
+                          "frac": round(BYTES_PER_UPDATE[storage] * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "bitwise_equal": same[cfg]}), flush=True)
 
 
 def main():

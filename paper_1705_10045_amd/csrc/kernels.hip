@@ -185,32 +185,32 @@ inline bool fits_buffer(const StepGeom& g, int Q, int storage_bytes)
     return (unsigned long long)g.plane * 2ull * Q * storage_bytes < (1ull << 32);
 }
 
-template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool CEARLY, bool STASH,
-          bool BUF, int NMODE>
+template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool STASH, bool BUF,
+          int NMODE>
 hipError_t launch_one(const void* src, void* dst, const StepGeom& g, const Phys& ph,
                       const StepAux& aux, hipStream_t st)
 {
     const unsigned nblk = (unsigned)(g.ntx * g.nty * g.nchunks);
-    hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, CEARLY, STASH>), dim3(nblk),
+    hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, STASH>), dim3(nblk),
                        dim3(NTH), 0, st, (const S*)src, (S*)dst, g, ph, aux);
     return hipGetLastError();
 }
 
 // Picks the instantiation for the run-time facts: buffer addressing if the state allows it,
 // and the tau = 1 collision (no re-read of N_k) when 1/tau is exactly 1.
-template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool CEARLY, bool STASH = false>
+template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool STASH = false>
 hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Phys& ph,
                          const StepAux& aux, hipStream_t st)
 {
     const bool tau1 = ph.omega == 1.0;
     if constexpr (sizeof(S) == 4) {
         if (fits_buffer(g, Q, 4)) {
-            return tau1 ? launch_one<Q, S, R, TX, TY, NTH, PIPE, CEARLY, STASH, true, kTauOne>(src, dst, g, ph, aux, st)
-                        : launch_one<Q, S, R, TX, TY, NTH, PIPE, CEARLY, false, true, kTauAny>(src, dst, g, ph, aux, st);
+            return tau1 ? launch_one<Q, S, R, TX, TY, NTH, PIPE, STASH, true, kTauOne>(src, dst, g, ph, aux, st)
+                        : launch_one<Q, S, R, TX, TY, NTH, PIPE, false, true, kTauAny>(src, dst, g, ph, aux, st);
         }
     }
-    return tau1 ? launch_one<Q, S, R, TX, TY, NTH, PIPE, CEARLY, STASH, false, kTauOne>(src, dst, g, ph, aux, st)
-                : launch_one<Q, S, R, TX, TY, NTH, PIPE, CEARLY, false, false, kTauAny>(src, dst, g, ph, aux, st);
+    return tau1 ? launch_one<Q, S, R, TX, TY, NTH, PIPE, STASH, false, kTauOne>(src, dst, g, ph, aux, st)
+                : launch_one<Q, S, R, TX, TY, NTH, PIPE, false, false, kTauAny>(src, dst, g, ph, aux, st);
 }
 
 }  // namespace
@@ -221,10 +221,10 @@ hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Ph
 // variant gives bitwise-identical results.
 // `per_cu` is the number of workgroups of the variant resident per compute unit (set by its
 // registers and LDS); the automatic z chunk aims at about 256 * per_cu workgroups.
-struct TileShape { int tx, ty, threads; bool pipe, cearly; int per_cu; };   // (+ stash: variant 0)
+struct TileShape { int tx, ty, threads; bool pipe, stash; int per_cu; };
 static const TileShape kVariants19f[] = {
-    {32, 16, 768, false, false, 1}, {32, 16, 768, false, false, 1}, {32, 8, 512, false, false, 2},
-    {32, 8, 256, false, false, 3},  {32, 8, 512, true, true, 1},   {32, 24, 1024, false, false, 1}};
+    {32, 16, 768, true, false, 1}, {32, 16, 768, false, true, 1}, {32, 16, 768, false, false, 1},
+    {32, 8, 512, false, false, 2}, {32, 8, 256, false, false, 3}};
 constexpr int kNumVariants19f = sizeof(kVariants19f) / sizeof(kVariants19f[0]);
 
 int step_variants(int Q, int storage_bytes) { return (Q == 19 && storage_bytes == 4) ? kNumVariants19f : 1; }
@@ -247,18 +247,17 @@ hipError_t launch_step(int Q, int storage_bytes, int variant, const void* src, v
 {
     if (Q == 19 && storage_bytes == 4) {
         switch (variant) {
-        case 0: return launch_step_t<19, float, float, 32, 16, 768, false, false, true>(src, dst, g, ph, aux, st);
-        case 1: return launch_step_t<19, float, float, 32, 16, 768, false, false>(src, dst, g, ph, aux, st);
-        case 2: return launch_step_t<19, float, float, 32, 8, 512, false, false>(src, dst, g, ph, aux, st);
-        case 3: return launch_step_t<19, float, float, 32, 8, 256, false, false>(src, dst, g, ph, aux, st);
-        case 4: return launch_step_t<19, float, float, 32, 8, 512, true, true>(src, dst, g, ph, aux, st);
-        case 5: return launch_step_t<19, float, float, 32, 24, 1024, false, false>(src, dst, g, ph, aux, st);
+        case 0: return launch_step_t<19, float, float, 32, 16, 768, true>(src, dst, g, ph, aux, st);
+        case 1: return launch_step_t<19, float, float, 32, 16, 768, false, true>(src, dst, g, ph, aux, st);
+        case 2: return launch_step_t<19, float, float, 32, 16, 768, false>(src, dst, g, ph, aux, st);
+        case 3: return launch_step_t<19, float, float, 32, 8, 512, false>(src, dst, g, ph, aux, st);
+        case 4: return launch_step_t<19, float, float, 32, 8, 256, false>(src, dst, g, ph, aux, st);
         default: return hipErrorInvalidValue;
         }
     }
-    if (Q == 19 && storage_bytes == 8) return launch_step_t<19, double, double, 32, 4, 128, false, false>(src, dst, g, ph, aux, st);
-    if (Q == 9 && storage_bytes == 4) return launch_step_t<9, float, float, 32, 8, 256, true, false>(src, dst, g, ph, aux, st);
-    if (Q == 9 && storage_bytes == 8) return launch_step_t<9, double, double, 32, 8, 256, false, false>(src, dst, g, ph, aux, st);
+    if (Q == 19 && storage_bytes == 8) return launch_step_t<19, double, double, 32, 4, 128, false>(src, dst, g, ph, aux, st);
+    if (Q == 9 && storage_bytes == 4) return launch_step_t<9, float, float, 32, 8, 256, true>(src, dst, g, ph, aux, st);
+    if (Q == 9 && storage_bytes == 8) return launch_step_t<9, double, double, 32, 8, 256, false>(src, dst, g, ph, aux, st);
     return hipErrorInvalidValue;
 }
 

@@ -78,7 +78,7 @@ k_pool_step(const SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ h
         aux.tab_s0 = s0;
         aux.tab_inv_ds = inv_ds;
         aux.err = errs + lo;
-        step_tile<19, float, float, kPoolTX, kPoolTY, kPoolTX * kPoolTY, false, true, kTauRuntime, false, false>(
+        step_tile<19, float, float, kPoolTX, kPoolTY, kPoolTX * kPoolTY, false, true, kTauRuntime, false>(
             src, dst, g, ph, aux, local);
     }
 }

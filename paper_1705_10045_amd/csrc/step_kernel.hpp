@@ -18,8 +18,9 @@
 //   C: energy source, collisions and the store for the plane two behind zm, on the tile.
 // D2Q9 runs the same code with a single plane (no z halo, no lag between the stages).
 //
-// Per-node quantities of the tile's own nodes (rho, j, E, T, p, F) stay in registers between
-// the stages; the moving populations of the own node are pulled again for the collision.
+// Per-node quantities of the tile's own nodes (rho, j, E, p, F) stay in registers between the
+// stages (T comes from its LDS ring); the moving populations of the own node are pulled again
+// for the collision, or kept in an LDS stash.
 //
 // Arithmetic: moments, EOS, Phi and the force in FP64 (the force is a small difference of
 // Phi^2 values); u*, the energy source and the collision in R; the rest populations close the
@@ -140,14 +141,13 @@ enum NMode : int {
 // moments and force stay in registers between the stages.
 //
 // PIPE: the pulls of the next plane's first moment slot are issued right after the current
-// plane's sums.  CEARLY: the collision's own pulls are issued at the top of the iteration,
-// together with the moment-stage pulls, so both memory round trips overlap.  STASH (tau = 1
+// plane's sums, so they are in flight during the force and collision stages.  STASH (tau = 1
 // only): the collision does not pull its energy populations again; the moment stage already
 // pulled them for the own node, and they wait in an LDS ring of two planes (each thread keeps
 // its plane in registers until the collision has consumed the older plane of the same ring
 // slot, then moves it there).
 template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool BUF, int NMODE,
-          bool CEARLY, bool STASH>
+          bool STASH>
 __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restrict__ dst,
                                           const StepGeom& g, const Phys& ph, const StepAux& aux,
                                           const int lb)
@@ -246,13 +246,14 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     const bool needN = NMODE == kTauAny || (NMODE == kTauRuntime && keepN != R(0));
 
     // register ring of the own node's moments: [0] newest plane ... [ZH] plane being collided
-    double o_rho[ZH + 1], o_E[ZH + 1], o_p[ZH + 1];
-    R o_jx[ZH + 1], o_jy[ZH + 1], o_jz[ZH + 1], o_T[ZH + 1];
-    R fcur[3] = {R(0), R(0), R(0)}, fprev[3] = {R(0), R(0), R(0)};
+    // (T of that plane is read from its LDS ring)
+    double o_rho[ZH + 1], o_E[ZH + 1];
+    R o_jx[ZH + 1], o_jy[ZH + 1], o_jz[ZH + 1], o_p[ZH + 1];
+    R fcur[3] = {R(0), R(0), R(0)}, fprev[3] = {R(0), R(0), R(0)};   // force, newest first
 #pragma unroll
     for (int q = 0; q <= ZH; ++q) {
         o_rho[q] = 1.0; o_jx[q] = o_jy[q] = o_jz[q] = R(0);
-        o_E[q] = 1.0; o_T[q] = R(1); o_p[q] = 0.0;
+        o_E[q] = 1.0; o_p[q] = R(0);
     }
 
     // pulls of moment slot r at plane zm: N_k(x, t) = N*_k(x - c_k), g likewise
@@ -314,11 +315,10 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
 #pragma unroll
             for (int q = ZH; q > 0; --q) {
                 o_rho[q] = o_rho[q - 1]; o_jx[q] = o_jx[q - 1]; o_jy[q] = o_jy[q - 1];
-                o_jz[q] = o_jz[q - 1]; o_E[q] = o_E[q - 1]; o_T[q] = o_T[q - 1];
-                o_p[q] = o_p[q - 1];
+                o_jz[q] = o_jz[q - 1]; o_E[q] = o_E[q - 1]; o_p[q] = o_p[q - 1];
             }
             o_rho[0] = dr; o_jx[0] = R(djx); o_jy[0] = R(djy); o_jz[0] = R(djz);
-            o_E[0] = dE; o_T[0] = T; o_p[0] = p;
+            o_E[0] = dE; o_p[0] = R(p);
         }
     };
 
@@ -370,12 +370,13 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         const int own = wrap_index(zc, g.nz) * nxy + oy * g.nx + ox;
 
         const double rho_d = o_rho[ZH], E_d = o_E[ZH];
-        const R rho = R(rho_d), E = R(E_d), T = o_T[ZH];
-        const double p = o_p[ZH];
-        const R* Fo = (ZH > 0) ? fprev : fcur;
+        const R rho = R(rho_d), E = R(E_d), T = sT[sc][oe];
+        const R p = o_p[ZH];
         const R inv_rho = R(1) / rho;
         const R ux = o_jx[ZH] * inv_rho, uy = o_jy[ZH] * inv_rho, uz = o_jz[ZH] * inv_rho;
-        const R dux = Fo[0] * inv_rho, duy = Fo[1] * inv_rho, duz = Fo[2] * inv_rho;
+        const R* Fo = (ZH > 0) ? fprev : fcur;
+        // shifted velocity u + du of the EDM, du = F / rho (eq:edm)
+        const R vx = ux + Fo[0] * inv_rho, vy = uy + Fo[1] * inv_rho, vz = uz + Fo[2] * inv_rho;
 
         // div u* by central differences on each axis (section 6.2)
         R div = R(0.5) * (sU[0][suc][of + 1] - sU[0][suc][of - 1]) +
@@ -383,7 +384,7 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         if constexpr (D == 3) div += R(0.5) * (sU[2][sucp][of] - sU[2][sucm][of]);
 
         R dE = R(0);
-        if (flags & kWork) dE -= R(p) * div;
+        if (flags & kWork) dE -= p * div;
         if (flags & kConduction) {
             const R Tc = sT[sc][oe];
             R acc = (rho + sRho[sc][oe + 1]) * (sT[sc][oe + 1] - Tc) -
@@ -405,7 +406,6 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             }
         }
 
-        const R vx = ux + dux, vy = uy + duy, vz = uz + duz;
         const R uu = ux * ux + uy * uy + uz * uz;
         const R vv = vx * vx + vy * vy + vz * vz;
         const R base_u = R(1) - R(1.5) * uu, base_v = R(1) - R(1.5) * vv;
@@ -472,14 +472,8 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         const int sj = jring(zm);
 
         // ---------------- M: moments, EOS, Phi on the tile + 2-halo of plane zm
-        // Loads complete in issue order, so the order of the requests is: this plane's
-        // moment pulls (unless prefetched), the collision's pulls, the next plane's prefetch.
-        // (every collision thread owns moment slot 0: the tile lies inside the region)
         if (m_e[0] >= 0) {
             if constexpr (!PIPE) load_slot(zm, 0, pn0, pe0);
-            if constexpr (CEARLY) {
-                if (collides) load_own_any(zc);
-            }
             moments(0, pn0, pe0, sm, sj);
             if constexpr (kStash) {
 #pragma unroll
@@ -544,7 +538,7 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
 
         // ---------------- C: energy source, collisions, store for plane zc = zm - dir ZH
         if (collides) {
-            if constexpr (!CEARLY) load_own_any(zc);
+            load_own_any(zc);
             if constexpr (NMODE == kTauOne) {
                 collide(zc, std::false_type{});
             } else if constexpr (NMODE == kTauAny) {
@@ -567,12 +561,12 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
 }
 
 template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool BUF, int NMODE,
-          bool CEARLY, bool STASH>
+          bool STASH>
 __global__ void __launch_bounds__(NTH)
 k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const Phys ph,
        const StepAux aux)
 {
-    step_tile<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, CEARLY, STASH>(
+    step_tile<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, STASH>(
         src, dst, g, ph, aux, xcd_logical_block(blockIdx.x, gridDim.x));
 }
 
