@@ -100,7 +100,9 @@ def cpu_baseline(case, budget_s=12.0):
 
 
 def copy_probe(gib=1.0, reps=5):
-    """A plain device-to-device copy of known size, for scaling rocprofv3 byte counters."""
+    """A plain device-to-device copy of known size, for scaling rocprofv3 byte counters, and the
+    bandwidth a plain copy of the step's state (2 x 19 float arrays at 128^3 and 256^3) reaches:
+    the practical ceiling of an access pattern that reads and writes every population once."""
     import torch
     n = int(gib * (1 << 30)) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -108,8 +110,28 @@ def copy_probe(gib=1.0, reps=5):
     for _ in range(reps):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
-                      "launches": reps}), flush=True)
+    out = {"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": reps}
+    del a, b
+    for edge in (128, 256):
+        m = 38 * edge ** 3
+        a = torch.ones(m, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        k = 20
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(k):
+            b.copy_(a)
+        end.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end) / k
+        out["state_copy_%d" % edge] = {"ms": round(ms, 4), "GB_per_s": round(2 * 4 * m / ms / 1e6, 1),
+                                       "mlups_equivalent": round(edge ** 3 / ms / 1e3, 1)}
+        del a, b
+    print(json.dumps(out), flush=True)
 
 
 def serving_bench(count=48, steps_range=(100, 1000), budget_gib=4.0, max_slots=64,
@@ -119,7 +141,9 @@ def serving_bench(count=48, steps_range=(100, 1000), budget_gib=4.0, max_slots=6
     500..5000 of the full request mix so the run stays short).  Three passes over the same
     request list: a burst (all arrive at t = 0) measures the batched capacity; a Poisson stream
     offered at `load` x that capacity gives p50/p99 time-to-result; the same requests one after
-    another with a single simulation each give the one-at-a-time rate."""
+    another with a single simulation each give the one-at-a-time rate.  Each request carries its
+    initial fields (built before the clock starts); upload, initialisation, the steps and the
+    download of the result fields are timed."""
     from paper_1705_10045_amd import inputs as I
     from paper_1705_10045_amd import lbm
     from paper_1705_10045_amd import serve
@@ -127,10 +151,12 @@ def serving_bench(count=48, steps_range=(100, 1000), budget_gib=4.0, max_slots=6
     reqs = I.serving_requests(count=count, steps_range=steps_range)
     work = np.array([r["edge"] ** 3 * r["steps"] for r in reqs], dtype=np.float64)
     budget = int(budget_gib * (1 << 30))
+    # the initial fields arrive with each request (the client builds them): not timed
+    payload = {r["id"]: I.request_fields(r) for r in reqs}
 
     def run(arrivals):
         with lbm.Pool(budget, max_slots=max_slots, steps_per_run=steps_per_run) as pool:
-            return serve.serve(reqs, arrivals, serve.PoolExecutor(pool))
+            return serve.serve(reqs, arrivals, serve.PoolExecutor(pool, payload=payload))
 
     print("serving: burst of %d requests" % count, file=sys.stderr, flush=True)
     burst = run(np.zeros(count))
@@ -138,7 +164,7 @@ def serving_bench(count=48, steps_range=(100, 1000), budget_gib=4.0, max_slots=6
     print("serving: Poisson stream at %.2f requests/s" % rate, file=sys.stderr, flush=True)
     stream = run(serve.poisson_arrivals(count, rate))
     print("serving: one at a time", file=sys.stderr, flush=True)
-    single = serve.one_at_a_time(reqs)
+    single = serve.one_at_a_time(reqs, payload=payload)
 
     def brief(r):
         return {"p50_s": round(r["p50_s"], 4), "p99_s": round(r["p99_s"], 4),

@@ -216,7 +216,7 @@ hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Ph
 }  // namespace
 
 // Launch shapes of the fused step.  Variant 0 is the default per (lattice, storage); the others
-// exist for FP32 D3Q19 (the bandwidth-critical path) and are selected for tuning.  Tile shape,
+// exist for D3Q19 (the bandwidth-critical paths) and are selected for tuning.  Tile shape,
 // thread count and the order of the loads do not change the per-node arithmetic, so every
 // variant gives bitwise-identical results.
 // `per_cu` is the number of workgroups of the variant resident per compute unit (set by its
@@ -226,19 +226,30 @@ static const TileShape kVariants19f[] = {
     {32, 16, 768, true, false, 1}, {32, 16, 768, false, true, 1}, {32, 16, 768, false, false, 1},
     {32, 8, 512, false, false, 2}, {32, 8, 256, false, false, 3}};
 constexpr int kNumVariants19f = sizeof(kVariants19f) / sizeof(kVariants19f[0]);
+// FP64 D3Q19: twice the registers and LDS per node
+static const TileShape kVariants19d[] = {
+    {32, 8, 512, false, false, 1}, {32, 8, 256, false, false, 1}, {32, 4, 128, false, false, 2}};
+constexpr int kNumVariants19d = sizeof(kVariants19d) / sizeof(kVariants19d[0]);
 
-int step_variants(int Q, int storage_bytes) { return (Q == 19 && storage_bytes == 4) ? kNumVariants19f : 1; }
+int step_variants(int Q, int storage_bytes)
+{
+    if (Q == 19) return storage_bytes == 4 ? kNumVariants19f : kNumVariants19d;
+    return 1;
+}
 
 void step_tile(int Q, int storage_bytes, int variant, int& tx, int& ty, int& per_cu)
 {
-    if (Q == 19 && storage_bytes == 4 && variant >= 0 && variant < kNumVariants19f) {
-        tx = kVariants19f[variant].tx;
-        ty = kVariants19f[variant].ty;
-        per_cu = kVariants19f[variant].per_cu;
+    const TileShape* t = nullptr;
+    if (Q == 19 && storage_bytes == 4 && variant >= 0 && variant < kNumVariants19f) t = &kVariants19f[variant];
+    if (Q == 19 && storage_bytes == 8 && variant >= 0 && variant < kNumVariants19d) t = &kVariants19d[variant];
+    if (t) {
+        tx = t->tx;
+        ty = t->ty;
+        per_cu = t->per_cu;
         return;
     }
     tx = 32;
-    ty = (Q == 19 && storage_bytes == 8) ? 4 : 8;
+    ty = 8;
     per_cu = 2;
 }
 
@@ -255,7 +266,14 @@ hipError_t launch_step(int Q, int storage_bytes, int variant, const void* src, v
         default: return hipErrorInvalidValue;
         }
     }
-    if (Q == 19 && storage_bytes == 8) return launch_step_t<19, double, double, 32, 4, 128, false>(src, dst, g, ph, aux, st);
+    if (Q == 19 && storage_bytes == 8) {
+        switch (variant) {
+        case 0: return launch_step_t<19, double, double, 32, 8, 512, false>(src, dst, g, ph, aux, st);
+        case 1: return launch_step_t<19, double, double, 32, 8, 256, false>(src, dst, g, ph, aux, st);
+        case 2: return launch_step_t<19, double, double, 32, 4, 128, false>(src, dst, g, ph, aux, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     if (Q == 9 && storage_bytes == 4) return launch_step_t<9, float, float, 32, 8, 256, true>(src, dst, g, ph, aux, st);
     if (Q == 9 && storage_bytes == 8) return launch_step_t<9, double, double, 32, 8, 256, false>(src, dst, g, ph, aux, st);
     return hipErrorInvalidValue;

@@ -27,9 +27,10 @@
 
 namespace lbm {
 
-constexpr int kPoolTX = 32, kPoolTY = 8;   // tile of the FP32 D3Q19 step
+constexpr int kPoolTX = 32, kPoolTY = 16;  // tile of the FP32 D3Q19 step, one moment slot per
+constexpr int kPoolThreads = 768;          // thread (no prefetch: both collisions are compiled in)
 constexpr int kPoolChunk = 16;             // z planes per tile: uniform tile work in the mix
-constexpr int kPoolGrid = 2048;            // workgroups of the persistent batched launch
+constexpr int kPoolGrid = 256;             // persistent workgroups: one per compute unit
 constexpr int kPoolMaxEdge = 128;
 
 struct SlotDesc {
@@ -49,7 +50,7 @@ struct PoolHeader {
     int total_tiles;
 };
 
-__global__ void __launch_bounds__(kPoolTX* kPoolTY)
+__global__ void __launch_bounds__(kPoolThreads)
 k_pool_step(const SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ hdr,
             const double* __restrict__ table, double s0, double inv_ds, int* __restrict__ errs)
 {
@@ -78,7 +79,7 @@ k_pool_step(const SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ h
         aux.tab_s0 = s0;
         aux.tab_inv_ds = inv_ds;
         aux.err = errs + lo;
-        step_tile<19, float, float, kPoolTX, kPoolTY, kPoolTX * kPoolTY, false, true, kTauRuntime, false>(
+        step_tile<19, float, float, kPoolTX, kPoolTY, kPoolThreads, false, true, kTauRuntime, false>(
             src, dst, g, ph, aux, local);
     }
 }
@@ -216,7 +217,7 @@ lbm_status capture_graph(lbm_pool* p)
     if (e != hipSuccess) return hip_fail(e, "graph capture begin");
     const int adv_blocks = (p->max_slots + 255) / 256;
     for (int i = 0; i < p->steps_per_run; ++i) {
-        hipLaunchKernelGGL(k_pool_step, dim3(kPoolGrid), dim3(kPoolTX * kPoolTY), 0, p->stream,
+        hipLaunchKernelGGL(k_pool_step, dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
                            p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
         hipLaunchKernelGGL(k_pool_advance, dim3(adv_blocks), dim3(256), 0, p->stream, p->d_slots,
                            p->d_hdr, p->d_errs);

@@ -46,12 +46,13 @@ def request_bytes_lower_bound(edge):
 class PoolExecutor:
     """Executor backed by the device pool.  A request that cannot fit (no free slot, or fewer
     free arena bytes than its buffers need) is declined without building its fields; a
-    request's initial fields are built once and kept until it is admitted."""
+    request's initial fields are built once and kept until it is admitted.  `payload`, if
+    given, maps a request id to fields that arrived with the request (built by the client)."""
 
-    def __init__(self, pool, physics=None):
+    def __init__(self, pool, physics=None, payload=None):
         self.pool = pool
         self.physics = physics or inputs.physics()
-        self._fields = {}
+        self._fields = dict(payload) if payload else {}
 
     def submit(self, req):
         st = self.pool.stats()
@@ -149,15 +150,16 @@ def serve(requests, arrivals, executor, clock=time.perf_counter, sleep=time.slee
     return report
 
 
-def one_at_a_time(requests, physics=None, clock=time.perf_counter):
+def one_at_a_time(requests, physics=None, clock=time.perf_counter, payload=None):
     """The same requests solved one after another with a single simulation each (lbm_init,
-    lbm_step, lbm_moments, lbm_free): aggregate node updates per second."""
+    lbm_step, lbm_moments, lbm_free): aggregate node updates per second.  `payload` as for
+    PoolExecutor."""
     from . import lbm
     physics = physics or inputs.physics()
     t0 = clock()
     total = 0
     for r in requests:
-        f = inputs.request_fields(r, physics)
+        f = payload[r["id"]] if payload else inputs.request_fields(r, physics)
         with lbm.Sim(19, f["params"], f["rho0"], f["u0"], f["T0"], storage_bytes=4) as s:
             s.step(r["steps"])
             s.moments()
