@@ -33,7 +33,8 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS (coupled density+energy) & % HBM roofline, 1 GPU; serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = {4: 2 * 19 * 2 * 4, 8: 2 * 19 * 2 * 8}
-KERNEL_SOURCES = ["paper_1705_10045_amd/csrc/step_kernel.hpp", "paper_1705_10045_amd/csrc/physics.hpp",
+KERNEL_SOURCES = ["paper_1705_10045_amd/csrc/step_kernel.hpp", "paper_1705_10045_amd/csrc/node_math.hpp",
+                  "paper_1705_10045_amd/csrc/physics.hpp",
                   "paper_1705_10045_amd/csrc/lattice.hpp", "paper_1705_10045_amd/csrc/kernels.hip",
                   "paper_1705_10045_amd/csrc/api.hip"]
 
@@ -100,9 +101,7 @@ def cpu_baseline(case, budget_s=12.0):
 
 
 def copy_probe(gib=1.0, reps=5):
-    """A plain device-to-device copy of known size, for scaling rocprofv3 byte counters, and the
-    bandwidth a plain copy of the step's state (2 x 19 float arrays at 128^3 and 256^3) reaches:
-    the practical ceiling of an access pattern that reads and writes every population once."""
+    """A plain device-to-device copy of known size, for scaling rocprofv3 byte counters."""
     import torch
     n = int(gib * (1 << 30)) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -110,9 +109,17 @@ def copy_probe(gib=1.0, reps=5):
     for _ in range(reps):
         b.copy_(a)
     torch.cuda.synchronize()
-    out = {"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": reps}
-    del a, b
-    for edge in (128, 256):
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                      "launches": reps}), flush=True)
+
+
+def copy_ceiling(edges=(128, 256), reps=20):
+    """Bandwidth of a plain device copy of the step's state (2 x 19 float arrays), timed with
+    events: the practical ceiling of an access pattern that reads and writes every population
+    once."""
+    import torch
+    out = {}
+    for edge in edges:
         m = 38 * edge ** 3
         a = torch.ones(m, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -120,14 +127,13 @@ def copy_probe(gib=1.0, reps=5):
             b.copy_(a)
         start = torch.cuda.Event(enable_timing=True)
         end = torch.cuda.Event(enable_timing=True)
-        k = 20
         torch.cuda.synchronize()
         start.record()
-        for _ in range(k):
+        for _ in range(reps):
             b.copy_(a)
         end.record()
         torch.cuda.synchronize()
-        ms = start.elapsed_time(end) / k
+        ms = start.elapsed_time(end) / reps
         out["state_copy_%d" % edge] = {"ms": round(ms, 4), "GB_per_s": round(2 * 4 * m / ms / 1e6, 1),
                                        "mlups_equivalent": round(edge ** 3 / ms / 1e3, 1)}
         del a, b
@@ -239,7 +245,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="droplet128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="1 GiB device copies only (calibration of rocprofv3 byte counters)")
+    ap.add_argument("--ceiling", action="store_true",
+                    help="time a plain device copy of the step's state at 128^3 and 256^3")
     ap.add_argument("--sweep", action="store_true",
                     help="time every tile variant x z-chunk of the step kernel (tuning)")
     ap.add_argument("--serving", action="store_true",
@@ -257,6 +266,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.ceiling:
+        copy_ceiling()
         return
 
     import torch

@@ -33,6 +33,7 @@
 
 #include "kernels.hpp"
 #include "lattice.hpp"
+#include "node_math.hpp"
 #include "physics.hpp"
 
 namespace lbm {
@@ -282,23 +283,10 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
 
     // moments, EOS and Phi of moment slot r (plane in ring slots sm, sj)
     auto moments = [&](int r, const S (&pn)[Q], const S (&pe)[Q], int sm, int sj) {
-        // moments summed in FP64 (exact for FP32 populations up to the final rounding)
-        double dr = 0.0, djx = 0.0, djy = 0.0, djz = 0.0, dE = 0.0;
-#pragma unroll
-        for (int k = 0; k < Q; ++k) {
-            const double n = double(pn[k]);
-            dr += n;
-            dE += double(pe[k]);
-            if (L::cx[k] == 1) djx += n; else if (L::cx[k] == -1) djx -= n;
-            if (L::cy[k] == 1) djy += n; else if (L::cy[k] == -1) djy -= n;
-            if (L::cz[k] == 1) djz += n; else if (L::cz[k] == -1) djz -= n;
-        }
-        const double dT = dE / (dr * ph.c_v);
-        const double Te = (flags & kBaro) ? ph.T0_baro : dT;
-        const double p = vdw_pressure(dr, Te, ph);
-        double phi2 = dr * kTheta - p;
-        const bool ok = phi2 > 0.0 && dr * ph.inv_rho_c < 3.0 && dr > 0.0 && dE == dE &&
-                        dE < 1e30;
+        double dr, djx, djy, djz, dE, dT, p, phi2;
+        bool ok;
+        moment_sums<Q>(pn, pe, dr, djx, djy, djz, dE);
+        eos_phi2(dr, dE, ph, flags, dT, p, phi2, ok);
         if (!ok) {
             atomicOr(aux.err, 1);
             phi2 = 0.0;
@@ -375,82 +363,32 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         const R inv_rho = R(1) / rho;
         const R ux = o_jx[ZH] * inv_rho, uy = o_jy[ZH] * inv_rho, uz = o_jz[ZH] * inv_rho;
         const R* Fo = (ZH > 0) ? fprev : fcur;
-        // shifted velocity u + du of the EDM, du = F / rho (eq:edm)
-        const R vx = ux + Fo[0] * inv_rho, vy = uy + Fo[1] * inv_rho, vz = uz + Fo[2] * inv_rho;
 
         // div u* by central differences on each axis (section 6.2)
         R div = R(0.5) * (sU[0][suc][of + 1] - sU[0][suc][of - 1]) +
                 R(0.5) * (sU[1][suc][of + FX] - sU[1][suc][of - FX]);
         if constexpr (D == 3) div += R(0.5) * (sU[2][sucp][of] - sU[2][sucm][of]);
+        const R dE = energy_source<D, R, EX>(p, div, rho, T, sRho[scm], sRho[sc], sRho[scp], sT[scm],
+                                             sT[sc], sT[scp], oe, cond_half, flags, ph, aux);
 
-        R dE = R(0);
-        if (flags & kWork) dE -= p * div;
-        if (flags & kConduction) {
-            const R Tc = sT[sc][oe];
-            R acc = (rho + sRho[sc][oe + 1]) * (sT[sc][oe + 1] - Tc) -
-                    (rho + sRho[sc][oe - 1]) * (Tc - sT[sc][oe - 1]) +
-                    (rho + sRho[sc][oe + EX]) * (sT[sc][oe + EX] - Tc) -
-                    (rho + sRho[sc][oe - EX]) * (Tc - sT[sc][oe - EX]);
-            if constexpr (D == 3)
-                acc += (rho + sRho[scp][oe]) * (sT[scp][oe] - Tc) -
-                       (rho + sRho[scm][oe]) * (Tc - sT[scm][oe]);
-            dE += cond_half * acc;
-        }
-        if (flags & kLatent) {
-            const double Te = (flags & kBaro) ? ph.T0_baro : double(T);
-            double r1, r2;
-            if (band_limits(Te * ph.inv_T_c, aux.maxwell, aux.tab_s0, aux.tab_inv_ds, ph.rho_c,
-                            r1, r2)) {
-                const double rd = double(rho);
-                if (rd > r1 && rd < r2) dE -= R(ph.rhoQ / (r2 - r1) * rd * double(div));
-            }
-        }
-
-        const R uu = ux * ux + uy * uy + uz * uz;
-        const R vv = vx * vx + vy * vy + vz * vz;
-        const R base_u = R(1) - R(1.5) * uu, base_v = R(1) - R(1.5) * vv;
-        // Both collisions as linear combinations of the equilibrium polynomials
-        // P_k(v) = w_k (1 + 3 c.v + 4.5 (c.v)^2 - 1.5 v^2) (eq:feq):
-        //   N'_k = rho P_k(v) - keepN rho P_k(u) + keepN N_k             (eq:lbe, eq:edm)
-        //   g'_k = gV P_k(v) + gU P_k(u) + (keepG + dE/E) g_k            (eq:gk, section 4)
-        // with (gV, gU) = (E, -keepG E) with pseudoforces, (0, E/tau_E) without.
-        const R nU = -keepN * rho;
-        const R gV = pseudo ? E : R(0);
-        const R gU = pseudo ? -keepG * E : omega_E * E;
-        const R gK = keepG + dE / E;
-        // The collision conserves mass and changes the energy by exactly dE (the BGK, EDM and
-        // pseudoforce increments sum to zero; dg(1) sums to dE).  The moving directions are
-        // computed from the equilibria and the rest populations close the balances in FP64
-        // over the values actually stored, so rounding of the lattice weights cannot create
-        // mass or energy.
-        double sumN = 0.0, sumG = 0.0;
+        NodeCollision<Q, S, R, WN> c;
+        c.setup(rho, E, ux, uy, uz, Fo[0], Fo[1], Fo[2], inv_rho, dE, keepN, keepG, omega_E,
+                pseudo);
 #pragma unroll
         for (int k = 1; k < Q; ++k) {
             const int ko = opposite<Q>(k);
             if (ko < k) continue;
-            // P_k and P_-k share the even part of the polynomial
-            const R w = R(weight<Q>(k));
-            const R cu = R(L::cx[k]) * ux + R(L::cy[k]) * uy + R(L::cz[k]) * uz;
-            const R cv = R(L::cx[k]) * vx + R(L::cy[k]) * vy + R(L::cz[k]) * vz;
-            const R eu = fma(R(4.5) * w, cu * cu, w * base_u), ou = R(3) * w * cu;
-            const R ev = fma(R(4.5) * w, cv * cv, w * base_v), ov = R(3) * w * cv;
-            const R Pu[2] = {eu + ou, eu - ou}, Pv[2] = {ev + ov, ev - ov};
-            const int kk[2] = {k, ko};
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int q = kk[h];
-                R nn = rho * Pv[h];
-                if constexpr (WN) nn = fma(keepN, pk_n[q], fma(nU, Pu[h], nn));
-                const R gn = fma(gK, pk_e[q], fma(gU, Pu[h], gV * Pv[h]));
-                const S nn_s = S(nn), gn_s = S(gn);
-                sumN += double(nn_s);
-                sumG += double(gn_s);
-                io.store(q, own, nn_s);
-                io.store(Q + q, own, gn_s);
-            }
+            S out[4];
+            c.dir_pair(k, pk_n, pk_e, out);
+            io.store(k, own, out[0]);
+            io.store(Q + k, own, out[1]);
+            io.store(ko, own, out[2]);
+            io.store(Q + ko, own, out[3]);
         }
-        io.store(0, own, S(rho_d - sumN));
-        io.store(Q, own, S(E_d + double(dE) - sumG));
+        S n0, g0;
+        c.rest(rho_d, E_d, dE, n0, g0);
+        io.store(0, own, n0);
+        io.store(Q, own, g0);
     };
 
     // Chunks march upward and downward alternately, so the two chunks on either side of a
@@ -501,28 +439,9 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             for (int r = 0; r < MF; ++r) {
                 if (f_f[r] < 0) continue;
                 const int e = f_e[r];
-                // force of section 3 in FP64 (a small difference of Phi^2 values):
-                // F = (1/alpha) sum_k G_k Phi_k (A Phi_k + (1 - 2A) Phi(x)) c_k, summed over
-                // pairs of opposite directions
-                const double Am = ph.A;
-                const double Bm = (1.0 - 2.0 * Am) * sPhi[sf][e];
-                double fx = 0.0, fy = 0.0, fz = 0.0;
-#pragma unroll
-                for (int k = 1; k < Q; ++k) {
-                    const int ko = opposite<Q>(k);
-                    if (ko < k) continue;
-                    const int slp = L::cz[k] == 0 ? sf : (L::cz[k] == 1 ? sfp : sfm);
-                    const int slm = L::cz[k] == 0 ? sf : (L::cz[k] == 1 ? sfm : sfp);
-                    const double pp = sPhi[slp][e + L::cx[k] + EX * L::cy[k]];
-                    const double pm = sPhi[slm][e - L::cx[k] - EX * L::cy[k]];
-                    double d = pp * fma(Am, pp, Bm) - pm * fma(Am, pm, Bm);
-                    if (force_coef<Q>(k) != 1.0) d *= force_coef<Q>(k);
-                    if (L::cx[k] == 1) fx += d; else if (L::cx[k] == -1) fx -= d;
-                    if (L::cy[k] == 1) fy += d; else if (L::cy[k] == -1) fy -= d;
-                    if (L::cz[k] == 1) fz += d; else if (L::cz[k] == -1) fz -= d;
-                }
-                const double ia = ph.inv_alpha;
-                const R Fx = R(fx * ia), Fy = R(fy * ia), Fz = R(fz * ia);
+                double fx, fy, fz;
+                force_at<Q, EX>(sPhi[sfm], sPhi[sf], sPhi[sfp], e, ph.A, ph.inv_alpha, fx, fy, fz);
+                const R Fx = R(fx), Fy = R(fy), Fz = R(fz);
                 const R inv_rho = R(1) / sRho[sf][e];
                 const int f = f_f[r];
                 sU[0][suf][f] = (sJ[0][sjf][e] + R(0.5) * Fx) * inv_rho;
