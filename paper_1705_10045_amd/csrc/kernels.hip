@@ -224,7 +224,7 @@ hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Ph
 struct TileShape { int tx, ty, threads; bool pipe, stash; int per_cu; };
 static const TileShape kVariants19f[] = {
     {32, 16, 768, true, false, 1}, {32, 16, 768, false, true, 1}, {32, 16, 768, false, false, 1},
-    {32, 8, 512, false, false, 2}, {32, 8, 256, false, false, 3}};
+    {32, 8, 512, false, false, 2}, {32, 8, 256, false, false, 2}};
 constexpr int kNumVariants19f = sizeof(kVariants19f) / sizeof(kVariants19f[0]);
 // FP64 D3Q19: twice the registers and LDS per node
 static const TileShape kVariants19d[] = {

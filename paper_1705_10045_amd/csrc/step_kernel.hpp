@@ -11,7 +11,8 @@
 //
 // Work decomposition: a workgroup owns a TX x TY column of nodes and marches through a chunk
 // of z planes (even chunks upward, odd chunks downward).  Per z iteration it runs three
-// stages separated by barriers:
+// stages, with a barrier after M and after F (and after C when the LDS rings are too short to
+// let the next iteration's M overlap it):
 //   M: pull 2Q populations and form rho, j, E, T, p, Phi for plane zm on the tile plus a
 //      2-node halo (LDS rings);
 //   F: force and u* for the plane one behind zm on the tile plus a 1-node halo (LDS ring);
@@ -162,7 +163,13 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     static_assert(NTH >= NC && NTH % 64 == 0, "one collision node per thread");
     constexpr int EX = TX + 4, EY = TY + 4, NE = EX * EY;   // moments: tile + 2-halo
     constexpr int FX = TX + 2, FY = TY + 2, NF = FX * FY;   // force/u*: tile + 1-halo
-    constexpr int RING = (D == 3) ? 4 : 1;  // planes of Phi, rho, T held (zc-1 .. zc+2)
+    constexpr bool kStash = STASH && NMODE == kTauOne && D == 3;
+    // Planes of Phi, rho, T held: the collision reads zc-1 .. zc+1 while the moment stage writes
+    // zc+2; with a fifth plane, the next iteration's moment stage (zc+3) cannot overwrite what
+    // a slower wave's collision still reads, and the barrier that closes an iteration is not
+    // needed (the stash variant has no LDS to spare for it).
+    constexpr bool kFiveRing = D == 3 && !kStash;
+    constexpr int RING = (D == 3) ? (kFiveRing ? 5 : 4) : 1;
     constexpr int JR = (D == 3) ? 2 : 1;    // planes of j held (zf, zf+1)
     constexpr int UR = (D == 3) ? 3 : 1;    // planes of u* held (zc-1 .. zc+1)
     // moment slots beyond the first NTH go to threads without collision work when they fit
@@ -176,10 +183,9 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     __shared__ R sT[RING][NE];
     __shared__ R sJ[3][JR][NE];
     __shared__ R sU[3][UR][NF];
-    constexpr bool kStash = STASH && NMODE == kTauOne && D == 3;
     __shared__ S sG[kStash ? 2 : 1][kStash ? Q - 1 : 1][kStash ? NC : 1];
 
-    auto ring = [](int z) { return (z + 4) & (RING - 1); };   // z >= -4
+    auto ring = [](int z) { return (z + 10) % RING; };        // z >= -10
     auto jring = [](int z) { return (z + 4) & (JR - 1); };
     auto uring = [](int z) { return (z + 6) % UR; };          // z >= -6
 
@@ -475,7 +481,7 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
                 for (int k = 1; k < Q; ++k) sG[zm & 1][k - 1][tid] = held[k - 1];
             }
         }
-        __syncthreads();
+        if constexpr (!kFiveRing) __syncthreads();
     }
 }
 
