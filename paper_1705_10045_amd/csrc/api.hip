@@ -36,6 +36,12 @@ lbm_status hip_fail(hipError_t e, const char* what)
     return e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE;
 }
 
+lbm_status use_device(int device)
+{
+    const hipError_t e = hipSetDevice(device);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "hipSetDevice");
+}
+
 // ------------------------------------------------------------------------------------------
 // Maxwell coexistence table (section 5 band limits), reduced van der Waals fluid.
 //
@@ -363,7 +369,10 @@ lbm_status lbm_init(const lbm_params* params, const double* rho0, const double* 
     s->phys = make_phys(*params);
     s->n = (long long)params->nx * params->ny * params->nz;
     s->plane = padded_plane(s->n);
-    hipGetDevice(&s->device);
+    if (hipError_t e = hipGetDevice(&s->device); e != hipSuccess) {
+        delete s;
+        return hip_fail(e, "hipGetDevice");
+    }
     if (stream) {
         s->stream = (hipStream_t)stream;
         s->own_stream = false;
@@ -381,10 +390,11 @@ lbm_status lbm_init(const lbm_params* params, const double* rho0, const double* 
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_partials, sizeof(double) * (5 * s->red_blocks + 8));
     if (e != hipSuccess) { lbm_status r = hip_fail(e, "hipMalloc(state)"); lbm_free(s); return r; }
     s->aux.err = s->d_err;
-    hipMemsetAsync(s->d_err, 0, sizeof(int) * 16, s->stream);
+    e = hipMemsetAsync(s->d_err, 0, sizeof(int) * 16, s->stream);
     // zero padding so checkpoints are deterministic
-    hipMemsetAsync(s->buf[0], 0, bytes, s->stream);
-    hipMemsetAsync(s->buf[1], 0, bytes, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->buf[0], 0, bytes, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->buf[1], 0, bytes, s->stream);
+    if (e != hipSuccess) { lbm_status r = hip_fail(e, "clear state"); lbm_free(s); return r; }
     st = upload_table(s);
     if (st != LBM_OK) { lbm_free(s); return st; }
 
@@ -398,7 +408,7 @@ lbm_status lbm_init(const lbm_params* params, const double* rho0, const double* 
         e = launch_init(s->p.lattice, s->p.storage_bytes, s->buf[0], d_fields, d_fields + s->n, d_fields + 4 * s->n,
                         s->p.nx, s->p.ny, s->p.nz, s->plane, s->p.c_v, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    hipFree(d_fields);
+    (void)hipFree(d_fields);
     if (e != hipSuccess) { lbm_status r = hip_fail(e, "initial state"); lbm_free(s); return r; }
     s->cur = 0;
     s->step = 0;
@@ -410,7 +420,7 @@ lbm_status lbm_step_async(lbm_sim* s, int nsteps)
 {
     clear_error();
     if (!s || nsteps < 0) { set_error("bad simulation handle or step count"); return LBM_EINVAL; }
-    hipSetDevice(s->device);
+    if (lbm_status sd = use_device(s->device); sd != LBM_OK) return sd;
     return enqueue_steps(s, nsteps);
 }
 
@@ -418,7 +428,7 @@ lbm_status lbm_check(lbm_sim* s)
 {
     clear_error();
     if (!s) { set_error("simulation is NULL"); return LBM_EINVAL; }
-    hipSetDevice(s->device);
+    if (lbm_status sd = use_device(s->device); sd != LBM_OK) return sd;
     return read_error_word(s);
 }
 
@@ -466,7 +476,7 @@ lbm_status lbm_moments_device(lbm_sim* s, double* rho, double* u_star, double* E
 {
     clear_error();
     if (!s) { set_error("simulation is NULL"); return LBM_EINVAL; }
-    hipSetDevice(s->device);
+    if (lbm_status sd = use_device(s->device); sd != LBM_OK) return sd;
     lbm_status st = ensure_scratch(s);
     if (st != LBM_OK) return st;
     hipError_t e = launch_moments(s->p.lattice, s->p.storage_bytes, s->buf[s->cur], s->d_scratch, s->p.nx,
@@ -479,7 +489,7 @@ lbm_status lbm_moments(lbm_sim* s, double* rho, double* u_star, double* E, doubl
 {
     clear_error();
     if (!s) { set_error("simulation is NULL"); return LBM_EINVAL; }
-    hipSetDevice(s->device);
+    if (lbm_status sd = use_device(s->device); sd != LBM_OK) return sd;
     lbm_status st = ensure_scratch(s);
     if (st != LBM_OK) return st;
     const long long n = s->n;
@@ -501,7 +511,7 @@ lbm_status lbm_reduce(lbm_sim* s, double out[5])
 {
     clear_error();
     if (!s || !out) { set_error("NULL argument"); return LBM_EINVAL; }
-    hipSetDevice(s->device);
+    if (lbm_status sd = use_device(s->device); sd != LBM_OK) return sd;
     double* d_out = s->d_partials + 5 * s->red_blocks;
     hipError_t e = launch_reduce(s->p.lattice, s->p.storage_bytes, s->buf[s->cur], s->n, s->plane, s->d_partials,
                                  s->red_blocks, d_out, s->stream);
@@ -526,7 +536,7 @@ lbm_status lbm_checkpoint(lbm_sim* s, void* host_buf, size_t cap, size_t* used)
     *used = sizeof(CheckpointHeader) + bytes;
     if (!host_buf) return LBM_OK;
     if (cap < *used) { set_error("checkpoint buffer too small (%zu < %zu)", cap, *used); return LBM_EINVAL; }
-    hipSetDevice(s->device);
+    if (lbm_status sd = use_device(s->device); sd != LBM_OK) return sd;
     CheckpointHeader h;
     memset(&h, 0, sizeof(h));
     memcpy(h.magic, "LBMCKPT1", 8);
@@ -553,7 +563,7 @@ lbm_status lbm_restore(lbm_sim* s, const void* host_buf, size_t len)
         set_error("checkpoint does not match this simulation's lattice, shape or storage");
         return LBM_EINVAL;
     }
-    hipSetDevice(s->device);
+    if (lbm_status sd = use_device(s->device); sd != LBM_OK) return sd;
     hipError_t e = hipMemcpyAsync(s->buf[s->cur], (const char*)host_buf + sizeof(h), bytes, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_err, 0, sizeof(int), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -565,15 +575,16 @@ lbm_status lbm_restore(lbm_sim* s, const void* host_buf, size_t len)
 lbm_status lbm_free(lbm_sim* s)
 {
     if (!s) return LBM_OK;
-    hipSetDevice(s->device);
-    if (s->stream) hipStreamSynchronize(s->stream);
-    if (s->buf[0]) hipFree(s->buf[0]);
-    if (s->buf[1]) hipFree(s->buf[1]);
-    if (s->d_err) hipFree(s->d_err);
-    if (s->d_partials) hipFree(s->d_partials);
-    if (s->d_table) hipFree(s->d_table);
-    if (s->d_scratch) hipFree(s->d_scratch);
-    if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
+    // release everything even if the device reports an error: nothing here can be retried
+    (void)hipSetDevice(s->device);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->buf[0]) (void)hipFree(s->buf[0]);
+    if (s->buf[1]) (void)hipFree(s->buf[1]);
+    if (s->d_err) (void)hipFree(s->d_err);
+    if (s->d_partials) (void)hipFree(s->d_partials);
+    if (s->d_table) (void)hipFree(s->d_table);
+    if (s->d_scratch) (void)hipFree(s->d_scratch);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
     return LBM_OK;
 }

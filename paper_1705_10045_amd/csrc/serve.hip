@@ -247,7 +247,10 @@ lbm_status lbm_pool_create(size_t hbm_budget_bytes, int max_slots, int steps_per
     double rv, rl;
     if (!host_band_limits(0.8, rv, rl)) { set_error("Maxwell table unavailable"); return LBM_EDEVICE; }
     lbm_pool* p = new lbm_pool();
-    hipGetDevice(&p->device);
+    if (hipError_t e = hipGetDevice(&p->device); e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipGetDevice");
+    }
     if (stream) {
         p->stream = (hipStream_t)stream;
     } else {
@@ -313,11 +316,11 @@ lbm_status lbm_pool_submit(lbm_pool* p, const lbm_params* params, const double* 
     const size_t half = state_bytes(*params);
     const size_t half_al = (half + kAlign - 1) / kAlign * kAlign;
     size_t off = 0;
+    if (lbm_status sd = use_device(p->device); sd != LBM_OK) return sd;
     if (!arena_alloc(p, 2 * half_al, off)) {
         set_error("request needs %zu bytes; %zu of %zu in use", 2 * half_al, p->in_use, p->budget);
         return LBM_EBUSY;
     }
-    hipSetDevice(p->device);
     PoolSlot& ps = p->slots[slot];
     ps.used = true;
     ps.offset = off;
@@ -360,7 +363,7 @@ lbm_status lbm_pool_run(lbm_pool* p)
 {
     clear_error();
     if (!p) { set_error("pool is NULL"); return LBM_EINVAL; }
-    hipSetDevice(p->device);
+    if (lbm_status sd = use_device(p->device); sd != LBM_OK) return sd;
     if (p->dirty) {
         lbm_status st = upload_table(p);
         if (st != LBM_OK) return st;
@@ -411,7 +414,7 @@ lbm_status lbm_pool_collect(lbm_pool* p, long long ticket, double* rho, double* 
     const int s = it->second;
     PoolSlot& ps = p->slots[s];
     const SlotDesc& d = p->table[s];
-    hipSetDevice(p->device);
+    if (lbm_status sd = use_device(p->device); sd != LBM_OK) return sd;
     const long long n = (long long)ps.params.nx * ps.params.ny * ps.params.nz;
     double* scr = p->d_scratch;
     double* d_us = scr + 7 * n;
@@ -454,18 +457,19 @@ lbm_status lbm_pool_stats(const lbm_pool* p, long long out[4])
 lbm_status lbm_pool_destroy(lbm_pool* p)
 {
     if (!p) return LBM_OK;
-    hipSetDevice(p->device);
-    if (p->stream) hipStreamSynchronize(p->stream);
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
-    if (p->arena) hipFree(p->arena);
-    if (p->d_slots) hipFree(p->d_slots);
-    if (p->d_hdr) hipFree(p->d_hdr);
-    if (p->d_errs) hipFree(p->d_errs);
-    if (p->d_staging) hipFree(p->d_staging);
-    if (p->d_scratch) hipFree(p->d_scratch);
-    if (p->d_table) hipFree(p->d_table);
-    if (p->own_stream && p->stream) hipStreamDestroy(p->stream);
+    // release everything even if the device reports an error: nothing here can be retried
+    (void)hipSetDevice(p->device);
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->arena) (void)hipFree(p->arena);
+    if (p->d_slots) (void)hipFree(p->d_slots);
+    if (p->d_hdr) (void)hipFree(p->d_hdr);
+    if (p->d_errs) (void)hipFree(p->d_errs);
+    if (p->d_staging) (void)hipFree(p->d_staging);
+    if (p->d_scratch) (void)hipFree(p->d_scratch);
+    if (p->d_table) (void)hipFree(p->d_table);
+    if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
     delete p;
     return LBM_OK;
 }

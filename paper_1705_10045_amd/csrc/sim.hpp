@@ -32,6 +32,8 @@ namespace lbm {
 void set_error(const char* fmt, ...);
 void clear_error();
 lbm_status hip_fail(hipError_t e, const char* what);
+// makes `device` current; LBM_EDEVICE with the message set if that fails
+lbm_status use_device(int device);
 bool host_band_limits(double Tr, double& rv, double& rl);
 Phys make_phys(const lbm_params& p);
 long long padded_plane(long long n);
