@@ -246,8 +246,9 @@ void choose_geometry(lbm_sim* s, int chunk_request)
     g.nty = (p.ny + ty - 1) / ty;
     int chunk = p.nz;
     if (p.lattice == 19) {
-        // about as many workgroups as the 256 compute units hold at once, z chunks of at most
-        // 32 planes: longer chunks re-read fewer halo planes, more workgroups balance the load
+        // about as many workgroups as the 256 compute units hold at once (one round), with the
+        // longest z chunks that allows: each chunk pulls 5 halo planes and runs 4 warm-up
+        // iterations, so longer chunks waste less (chunks of at least 4 planes)
         const long long cols = (long long)g.ntx * g.nty;
         const long long target = 256LL * per_cu;
         long long want = (target + cols - 1) / cols;
@@ -255,7 +256,6 @@ void choose_geometry(lbm_sim* s, int chunk_request)
         if (want > maxc) want = maxc;
         if (want < 1) want = 1;
         chunk = (int)((p.nz + want - 1) / want);
-        if (chunk > 32) chunk = 32;
         if (chunk_request > 0) chunk = chunk_request < p.nz ? chunk_request : p.nz;
     }
     g.chunk = chunk;
