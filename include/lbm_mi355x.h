@@ -126,10 +126,11 @@ const char* lbm_last_error(void);
  * number of workgroups per step (for profiling reports). */
 lbm_status lbm_launch_info(const lbm_sim* sim, int info[4]);
 
-/* Select the tile shape (variant 0 .. n-1; FP32 D3Q19 has several, other configurations one)
- * and the z-chunk length (0 = automatic) of the fused step kernel.  Results do not depend on
- * the choice (the per-node arithmetic is the same); only speed does.  LBM_EINVAL for an
- * unknown variant. */
+/* Select the launch variant of the fused step kernel (0 .. n-1: tile shape, threads per
+ * workgroup, prefetch or LDS stash; D3Q19 has several in each precision, D2Q9 one; 0 is the
+ * default) and the z-chunk length (0 = automatic).  Results do not depend on the choice (the
+ * per-node arithmetic is the same); only speed does.  LBM_EINVAL for an unknown variant or a
+ * negative chunk. */
 lbm_status lbm_set_launch(lbm_sim* sim, int variant, int chunk);
 
 /* Velocity set used by the library (section 2) and the force coefficients of section 3:
