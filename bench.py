@@ -63,6 +63,12 @@ def workload(name):
                                "storage": "fp64" if storage == 8 else "fp32", "T_over_Tc": 0.75,
                                "rho_mean": 1.0, "noise_sigma": 0.02,
                                "terms": "work+conduction+latent+pseudoforces"}
+    if name == "spinodal512":
+        case = I.spinodal_3d(n=512, Tr=0.75, rho_mean=1.0, sigma=0.02)
+        return case, 4, {"workload": "d3q19_spinodal_512^3_fp32", "lattice": "D3Q19",
+                         "shape": [512, 512, 512], "storage": "fp32", "T_over_Tc": 0.75,
+                         "rho_mean": 1.0, "noise_sigma": 0.02,
+                         "terms": "work+conduction+latent+pseudoforces"}
     raise SystemExit("unknown workload %s" % name)
 
 

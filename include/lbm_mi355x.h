@@ -68,7 +68,8 @@ typedef struct lbm_sim lbm_sim;
  * g_k = geq_k(rho0 c_v T0, u0) (eq:feq with E in place of rho, section 4).
  * rho0[n], u0[3n], T0[n]: host FP64 fields.  stream: a hipStream_t on the current device on
  * which every later call enqueues its work, or NULL for a library-created stream.
- * Rejects (LBM_EINVAL) tau or tau_E <= 1/2, lattice/shape mismatch, chi >= 0.5/d with
+ * Rejects (LBM_EINVAL) tau or tau_E <= 1/2, lattice/shape mismatch, a box whose population
+ * plane (nx*ny*nz values) would exceed 4 GB (beyond any state that fits in HBM), chi >= 0.5/d with
  * conduction on (d = number of axes with extent > 1; section 6.1), a non-positive or
  * non-finite field, rho0/rho_c >= 3, Phi^2 = rho theta - p <= 0 at any node (section 3), and
  * an initial field violating (dp/drho)_T <= (h/dt)^2 + theta (section 3). */

@@ -198,6 +198,12 @@ lbm_status validate_params(const lbm_params* p)
         return LBM_EINVAL;
     }
     if ((p->flags & LBM_BAROTROPIC) && !(p->T0_baro > 0)) { set_error("barotropic EOS needs T0_baro > 0"); return LBM_EINVAL; }
+    // the step addresses nodes within one population plane with 32-bit byte offsets
+    const long long n = (long long)p->nx * p->ny * p->nz;
+    if ((unsigned long long)padded_plane(n) * (unsigned long long)p->storage_bytes >= (1ull << 32)) {
+        set_error("one population plane of %lld nodes exceeds 4 GB", n);
+        return LBM_EINVAL;
+    }
     if ((p->flags & LBM_LATENT) && !maxwell_table().ok) { set_error("Maxwell table construction failed"); return LBM_EDEVICE; }
     return LBM_OK;
 }

@@ -198,12 +198,13 @@ hipError_t launch_one(const void* src, void* dst, const StepGeom& g, const Phys&
 
 // Picks the instantiation for the run-time facts: buffer addressing if the state allows it,
 // and the tau = 1 collision (no re-read of N_k) when 1/tau is exactly 1.
-template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool STASH = false>
+template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool STASH = false,
+          bool GLOBAL = false>
 hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Phys& ph,
                          const StepAux& aux, hipStream_t st)
 {
     const bool tau1 = ph.omega == 1.0;
-    if constexpr (sizeof(S) == 4) {
+    if constexpr (sizeof(S) == 4 && !GLOBAL) {
         if (fits_buffer(g, Q, 4)) {
             return tau1 ? launch_one<Q, S, R, TX, TY, NTH, PIPE, STASH, true, kTauOne>(src, dst, g, ph, aux, st)
                         : launch_one<Q, S, R, TX, TY, NTH, PIPE, false, true, kTauAny>(src, dst, g, ph, aux, st);
@@ -221,10 +222,12 @@ hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Ph
 // variant gives bitwise-identical results.
 // `per_cu` is the number of workgroups of the variant resident per compute unit (set by its
 // registers and LDS); the automatic z chunk aims at about 256 * per_cu workgroups.
+// The last FP32 variant is the default launch with plain global addressing, which states of 4 GB
+// and more use automatically (512^3 and up).
 struct TileShape { int tx, ty, threads; bool pipe, stash; int per_cu; };
 static const TileShape kVariants19f[] = {
     {32, 16, 768, true, false, 1}, {32, 16, 768, false, true, 1}, {32, 16, 768, false, false, 1},
-    {32, 8, 512, false, false, 2}, {32, 8, 256, false, false, 2}};
+    {32, 8, 512, false, false, 2}, {32, 8, 256, false, false, 2}, {32, 16, 768, true, false, 1}};
 constexpr int kNumVariants19f = sizeof(kVariants19f) / sizeof(kVariants19f[0]);
 // FP64 D3Q19: twice the registers and LDS per node
 static const TileShape kVariants19d[] = {
@@ -263,6 +266,7 @@ hipError_t launch_step(int Q, int storage_bytes, int variant, const void* src, v
         case 2: return launch_step_t<19, float, float, 32, 16, 768, false>(src, dst, g, ph, aux, st);
         case 3: return launch_step_t<19, float, float, 32, 8, 512, false>(src, dst, g, ph, aux, st);
         case 4: return launch_step_t<19, float, float, 32, 8, 256, false>(src, dst, g, ph, aux, st);
+        case 5: return launch_step_t<19, float, float, 32, 16, 768, true, false, true>(src, dst, g, ph, aux, st);
         default: return hipErrorInvalidValue;
         }
     }

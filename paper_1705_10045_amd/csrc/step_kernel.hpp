@@ -82,7 +82,8 @@ __device__ __forceinline__ void region_slot(int s, int& rx, int& ry)
 // Access to population (set*Q + k) at node i of the two buffers.  With BUF the state (< 4 GB)
 // is addressed through buffer resources: the node offset is a 32-bit per-lane byte offset and
 // the plane offset of the population a scalar offset, so no per-access 64-bit address
-// arithmetic is spent.  Otherwise plain global pointers.  Stores are marked non-temporal
+// arithmetic is spent.  Otherwise global pointers with a scalar plane base.  Stores are marked
+// non-temporal
 // (nothing in the step reads them back), so they do not displace the halo and re-read data the
 // step still needs from L2.
 template <class S, bool BUF>
@@ -94,10 +95,17 @@ struct PopIO<S, false> {
     S* __restrict__ dst;
     long long plane;
     __device__ PopIO(const S* s, S* d, long long p, int) : src(s), dst(d), plane(p) {}
-    __device__ __forceinline__ S load(int pk, int i) const { return src[(long long)pk * plane + i]; }
+    // the plane base is uniform and the node offset a 32-bit unsigned byte offset (a plane is
+    // under 4 GB), so a load is one global_load with a scalar base and a 32-bit lane offset
+    __device__ __forceinline__ S load(int pk, int i) const
+    {
+        const char* base = (const char*)(src + (long long)pk * plane);
+        return *(const S*)(base + (unsigned)i * (unsigned)sizeof(S));
+    }
     __device__ __forceinline__ void store(int pk, int i, S v) const
     {
-        __builtin_nontemporal_store(v, dst + (long long)pk * plane + i);
+        char* base = (char*)(dst + (long long)pk * plane);
+        __builtin_nontemporal_store(v, (S*)(base + (unsigned)i * (unsigned)sizeof(S)));
     }
 };
 

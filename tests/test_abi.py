@@ -1,6 +1,7 @@
 """The C-ABI library: it loads without a GPU, exports every entry point declared in
 include/*.h, and its host-only pieces (lattice tables, Maxwell table, parameter and field
 validation) behave as documented.  No kernel is launched here."""
+import ctypes
 import glob
 import os
 import re
@@ -109,3 +110,15 @@ def test_footprint():
     fp = lbm.lbm_footprint_bytes(p)
     assert fp >= 2 * 2 * 19 * 128 ** 3 * 4
     assert fp < 2 * 2 * 19 * 128 ** 3 * 4 * 1.01
+
+
+def test_init_rejects_a_population_plane_over_4gb():
+    """The step addresses nodes within one population plane with 32-bit byte offsets: a box whose
+    plane exceeds 4 GB (far beyond what fits in HBM anyway) is refused before any field is read."""
+    phys, rho, u, T = _case()
+    p = lbm.make_params(19, (1024, 1024, 1024), phys, storage_bytes=4)
+    h = ctypes.c_void_p()
+    st = lbm.lib().lbm_init(ctypes.byref(p), None, None, None, None, ctypes.byref(h))
+    assert st == lbm.LBM_EINVAL
+    assert "4 GB" in lbm.lbm_last_error()
+    assert not h.value
