@@ -197,7 +197,13 @@ hipError_t launch_one(const void* src, void* dst, const StepGeom& g, const Phys&
 }
 
 // Picks the instantiation for the run-time facts: buffer addressing if the state allows it,
-// and the tau = 1 collision (no re-read of N_k) when 1/tau is exactly 1.
+// and the tau = 1 collision (no re-read of N_k) when 1/tau is exactly 1.  Where a variant asks
+// for the LDS stash, it is used where it measured faster on MI355X and fits the registers:
+//   - FP32 with buffer addressing, any tau; the density prefetch stays on for tau = 1 only
+//     (re-reading N_k in the collision leaves no registers for it);
+//   - FP64 (global addressing) for tau = 1 (with a collision that re-reads N_k it spills);
+//   - not with FP32 global addressing (states of 4 GB and more), where the prefetch alone is
+//     faster.
 template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool STASH = false,
           bool GLOBAL = false>
 hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Phys& ph,
@@ -207,10 +213,11 @@ hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Ph
     if constexpr (sizeof(S) == 4 && !GLOBAL) {
         if (fits_buffer(g, Q, 4)) {
             return tau1 ? launch_one<Q, S, R, TX, TY, NTH, PIPE, STASH, true, kTauOne>(src, dst, g, ph, aux, st)
-                        : launch_one<Q, S, R, TX, TY, NTH, PIPE, false, true, kTauAny>(src, dst, g, ph, aux, st);
+                        : launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, true, kTauAny>(src, dst, g, ph, aux, st);
         }
     }
-    return tau1 ? launch_one<Q, S, R, TX, TY, NTH, PIPE, STASH, false, kTauOne>(src, dst, g, ph, aux, st)
+    constexpr bool kStashGlobal = STASH && sizeof(S) == 8;
+    return tau1 ? launch_one<Q, S, R, TX, TY, NTH, PIPE, kStashGlobal, false, kTauOne>(src, dst, g, ph, aux, st)
                 : launch_one<Q, S, R, TX, TY, NTH, PIPE, false, false, kTauAny>(src, dst, g, ph, aux, st);
 }
 
@@ -222,16 +229,18 @@ hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Ph
 // variant gives bitwise-identical results.
 // `per_cu` is the number of workgroups of the variant resident per compute unit (set by its
 // registers and LDS); the automatic z chunk aims at about 256 * per_cu workgroups.
-// The last FP32 variant is the default launch with plain global addressing, which states of 4 GB
+// FP32 variant 5 is the default launch with plain global addressing, which states of 4 GB
 // and more use automatically (512^3 and up).
 struct TileShape { int tx, ty, threads; bool pipe, stash; int per_cu; };
 static const TileShape kVariants19f[] = {
-    {32, 16, 768, true, false, 1}, {32, 16, 768, false, true, 1}, {32, 16, 768, false, false, 1},
-    {32, 8, 512, false, false, 2}, {32, 8, 256, false, false, 2}, {32, 16, 768, true, false, 1}};
+    {32, 16, 768, true, true, 1}, {32, 16, 768, false, true, 1}, {32, 16, 768, true, false, 1},
+    {32, 16, 768, false, false, 1}, {32, 8, 512, false, false, 2}, {32, 16, 768, true, true, 1},
+    {32, 8, 256, false, false, 2}};
 constexpr int kNumVariants19f = sizeof(kVariants19f) / sizeof(kVariants19f[0]);
 // FP64 D3Q19: twice the registers and LDS per node
 static const TileShape kVariants19d[] = {
-    {32, 8, 512, false, false, 1}, {32, 8, 256, false, false, 1}, {32, 4, 128, false, false, 2}};
+    {32, 8, 512, false, true, 1}, {32, 8, 512, false, false, 1}, {32, 8, 256, false, false, 1},
+    {32, 4, 128, false, false, 2}};
 constexpr int kNumVariants19d = sizeof(kVariants19d) / sizeof(kVariants19d[0]);
 
 int step_variants(int Q, int storage_bytes)
@@ -261,20 +270,22 @@ hipError_t launch_step(int Q, int storage_bytes, int variant, const void* src, v
 {
     if (Q == 19 && storage_bytes == 4) {
         switch (variant) {
-        case 0: return launch_step_t<19, float, float, 32, 16, 768, true>(src, dst, g, ph, aux, st);
+        case 0: return launch_step_t<19, float, float, 32, 16, 768, true, true>(src, dst, g, ph, aux, st);
         case 1: return launch_step_t<19, float, float, 32, 16, 768, false, true>(src, dst, g, ph, aux, st);
-        case 2: return launch_step_t<19, float, float, 32, 16, 768, false>(src, dst, g, ph, aux, st);
-        case 3: return launch_step_t<19, float, float, 32, 8, 512, false>(src, dst, g, ph, aux, st);
-        case 4: return launch_step_t<19, float, float, 32, 8, 256, false>(src, dst, g, ph, aux, st);
-        case 5: return launch_step_t<19, float, float, 32, 16, 768, true, false, true>(src, dst, g, ph, aux, st);
+        case 2: return launch_step_t<19, float, float, 32, 16, 768, true>(src, dst, g, ph, aux, st);
+        case 3: return launch_step_t<19, float, float, 32, 16, 768, false>(src, dst, g, ph, aux, st);
+        case 4: return launch_step_t<19, float, float, 32, 8, 512, false>(src, dst, g, ph, aux, st);
+        case 5: return launch_step_t<19, float, float, 32, 16, 768, true, true, true>(src, dst, g, ph, aux, st);
+        case 6: return launch_step_t<19, float, float, 32, 8, 256, false>(src, dst, g, ph, aux, st);
         default: return hipErrorInvalidValue;
         }
     }
     if (Q == 19 && storage_bytes == 8) {
         switch (variant) {
-        case 0: return launch_step_t<19, double, double, 32, 8, 512, false>(src, dst, g, ph, aux, st);
-        case 1: return launch_step_t<19, double, double, 32, 8, 256, false>(src, dst, g, ph, aux, st);
-        case 2: return launch_step_t<19, double, double, 32, 4, 128, false>(src, dst, g, ph, aux, st);
+        case 0: return launch_step_t<19, double, double, 32, 8, 512, false, true>(src, dst, g, ph, aux, st);
+        case 1: return launch_step_t<19, double, double, 32, 8, 512, false>(src, dst, g, ph, aux, st);
+        case 2: return launch_step_t<19, double, double, 32, 8, 256, false>(src, dst, g, ph, aux, st);
+        case 3: return launch_step_t<19, double, double, 32, 4, 128, false>(src, dst, g, ph, aux, st);
         default: return hipErrorInvalidValue;
         }
     }

@@ -14,7 +14,8 @@
 // stages, with a barrier after M and after F (and after C when the LDS rings are too short to
 // let the next iteration's M overlap it):
 //   M: pull 2Q populations and form rho, j, E, T, p, Phi for plane zm on the tile plus a
-//      2-node halo (LDS rings);
+//      2-node halo (LDS rings; Phi is kept on the whole region, rho, T and j only on the tile
+//      plus a 1-node halo, the part that the force and the energy source read);
 //   F: force and u* for the plane one behind zm on the tile plus a 1-node halo (LDS ring);
 //   C: energy source, collisions and the store for the plane two behind zm, on the tile.
 // D2Q9 runs the same code with a single plane (no z halo, no lag between the stages).
@@ -151,11 +152,12 @@ enum NMode : int {
 // moments and force stay in registers between the stages.
 //
 // PIPE: the pulls of the next plane's first moment slot are issued right after the current
-// plane's sums, so they are in flight during the force and collision stages.  STASH (tau = 1
-// only): the collision does not pull its energy populations again; the moment stage already
-// pulled them for the own node, and they wait in an LDS ring of two planes (each thread keeps
-// its plane in registers until the collision has consumed the older plane of the same ring
-// slot, then moves it there).
+// plane's sums, so they are in flight during the force and collision stages.  STASH (D3Q19):
+// the collision does not pull its energy populations again; the moment stage already pulled
+// them for the own node, and they wait in an LDS ring of two planes (each thread keeps its
+// plane in registers until its collision has read the older plane of the same ring slot, then
+// moves it there).  With the stash, the prefetch covers the density populations only (the
+// energy pulls already occupy registers until the collision).
 template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool BUF, int NMODE,
           bool STASH>
 __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restrict__ dst,
@@ -171,12 +173,12 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     static_assert(NTH >= NC && NTH % 64 == 0, "one collision node per thread");
     constexpr int EX = TX + 4, EY = TY + 4, NE = EX * EY;   // moments: tile + 2-halo
     constexpr int FX = TX + 2, FY = TY + 2, NF = FX * FY;   // force/u*: tile + 1-halo
-    constexpr bool kStash = STASH && NMODE == kTauOne && D == 3;
+    constexpr bool kStash = STASH && D == 3;
     // Planes of Phi, rho, T held: the collision reads zc-1 .. zc+1 while the moment stage writes
     // zc+2; with a fifth plane, the next iteration's moment stage (zc+3) cannot overwrite what
     // a slower wave's collision still reads, and the barrier that closes an iteration is not
-    // needed (the stash variant has no LDS to spare for it).
-    constexpr bool kFiveRing = D == 3 && !kStash;
+    // needed.
+    constexpr bool kFiveRing = D == 3;
     constexpr int RING = (D == 3) ? (kFiveRing ? 5 : 4) : 1;
     constexpr int JR = (D == 3) ? 2 : 1;    // planes of j held (zf, zf+1)
     constexpr int UR = (D == 3) ? 3 : 1;    // planes of u* held (zc-1 .. zc+1)
@@ -187,9 +189,9 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     constexpr int MF = (NF + NTH - 1) / NTH;
 
     __shared__ double sPhi[RING][NE];
-    __shared__ R sRho[RING][NE];
-    __shared__ R sT[RING][NE];
-    __shared__ R sJ[3][JR][NE];
+    __shared__ R sRho[RING][NF];
+    __shared__ R sT[RING][NF];
+    __shared__ R sJ[3][JR][NF];
     __shared__ R sU[3][UR][NF];
     __shared__ S sG[kStash ? 2 : 1][kStash ? Q - 1 : 1][kStash ? NC : 1];
 
@@ -205,21 +207,25 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     const int z1 = min(z0 + g.chunk, g.nz);
     const int nxy = g.nx * g.ny;
 
-    // moment-stage slots of this thread: LDS index and wrapped x / y*nx of (node - c) for
-    // c = +1, 0, -1 (index 1 - c); m_e < 0 marks no slot
-    int m_e[ME];
+    // moment-stage slots of this thread: LDS index on the 2-halo region, on the 1-halo region
+    // (m_f < 0 outside it) and wrapped x / y*nx of (node - c) for c = +1, 0, -1 (index 1 - c);
+    // m_e < 0 marks no slot
+    int m_e[ME], m_f[ME];
     int m_x[ME][3], m_y[ME][3];
 #pragma unroll
     for (int r = 0; r < ME; ++r) {
         int s = tid + r * NTH;
         if constexpr (SPARE) s = r == 0 ? tid : (tid >= NC ? NTH + (tid - NC) : NE);
         m_e[r] = -1;
+        m_f[r] = -1;
         m_x[r][0] = m_x[r][1] = m_x[r][2] = 0;
         m_y[r][0] = m_y[r][1] = m_y[r][2] = 0;
         if (s < NE) {
             int ex, ey;
             region_slot<TX, TY, 2>(s, ex, ey);
             m_e[r] = ex + EX * ey;
+            if (ex >= 1 && ex <= EX - 2 && ey >= 1 && ey <= EY - 2)
+                m_f[r] = (ex - 1) + FX * (ey - 1);
             const int gx = wrap_index(x0 - 2 + ex, g.nx);
             const int gy = wrap_index(y0 - 2 + ey, g.ny);
             m_x[r][0] = wrap_index(gx - 1, g.nx);
@@ -240,14 +246,13 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             int fx, fy;
             region_slot<TX, TY, 1>(s, fx, fy);
             f_f[r] = fx + FX * fy;
-            f_e[r] = (fx + 1) + EX * (fy + 1);
+            f_e[r] = (fx + 1) + EX * (fy + 1);   // the same node on the 2-halo region
         }
     }
     // this thread's own node (slot 0 of every stage)
     const int otx = tid % TX, oty = tid / TX;
     const int ox = x0 + otx, oy = y0 + oty;
     const bool own_in_xy = tid < NC && ox < g.nx && oy < g.ny;
-    const int oe = (otx + 2) + EX * (oty + 2);
     const int of = (otx + 1) + FX * (oty + 1);
     const int xs[3] = {m_x[0][0], m_x[0][1], m_x[0][2]};   // slot 0 is the own node
     const int ys[3] = {m_y[0][0], m_y[0][1], m_y[0][2]};
@@ -271,8 +276,10 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         o_E[q] = 1.0; o_p[q] = R(0);
     }
 
-    // pulls of moment slot r at plane zm: N_k(x, t) = N*_k(x - c_k), g likewise
-    auto load_slot = [&](int zm, int r, S (&pn)[Q], S (&pe)[Q]) {
+    // pulls of moment slot r at plane zm: N_k(x, t) = N*_k(x - c_k), g likewise (`sets`: bit 0
+    // the density populations, bit 1 the energy populations)
+    auto load_slot = [&](int zm, int r, S (&pn)[Q], S (&pe)[Q], auto sets) {
+        constexpr int SETS = decltype(sets)::value;
         int zoff[3];
         if constexpr (D == 3) {
             zoff[0] = wrap_index(zm - 1, g.nz) * nxy;
@@ -290,8 +297,8 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
             const int off = row[1 - L::cz[k]][1 - L::cy[k]] + m_x[r][1 - L::cx[k]];
-            pn[k] = io.load(k, off);
-            pe[k] = io.load(Q + k, off);
+            if constexpr (SETS & 1) pn[k] = io.load(k, off);
+            if constexpr (SETS & 2) pe[k] = io.load(Q + k, off);
         }
     };
 
@@ -305,14 +312,15 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             atomicOr(aux.err, 1);
             phi2 = 0.0;
         }
-        const R rho = R(dr), T = R(dT);
-        const int e = m_e[r];
-        sPhi[sm][e] = sqrt(phi2);
-        sRho[sm][e] = rho;
-        sT[sm][e] = T;
-        sJ[0][sj][e] = R(djx);
-        sJ[1][sj][e] = R(djy);
-        sJ[2][sj][e] = R(djz);
+        sPhi[sm][m_e[r]] = sqrt(phi2);
+        const int f = m_f[r];
+        if (f >= 0) {
+            sRho[sm][f] = R(dr);
+            sT[sm][f] = R(dT);
+            sJ[0][sj][f] = R(djx);
+            sJ[1][sj][f] = R(djy);
+            sJ[2][sj][f] = R(djz);
+        }
         if (r == 0) {
 #pragma unroll
             for (int q = ZH; q > 0; --q) {
@@ -325,10 +333,18 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     };
 
     // the own node's pulls for the collision at plane zc (moving directions; the rest ones
-    // follow from the balances)
+    // follow from the balances); with the stash the energy populations come from LDS
     R pk_n[Q], pk_e[Q];
     auto load_own = [&](int zc, auto with_n) {
         constexpr bool WN = decltype(with_n)::value;
+        if constexpr (kStash) {
+#pragma unroll
+            for (int k = 1; k < Q; ++k) {
+                pk_e[k] = R(sG[zc & 1][k - 1][tid]);
+                pk_n[k] = R(0);
+            }
+            if constexpr (!WN) return;
+        }
         const int zoc = wrap_index(zc, g.nz) * nxy;
         int zpull[3] = {zoc, zoc, zoc};
         if constexpr (D == 3) {
@@ -343,18 +359,12 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
 #pragma unroll
         for (int k = 1; k < Q; ++k) {
             const int off = row[1 - L::cz[k]][1 - L::cy[k]] + xs[1 - L::cx[k]];
-            pk_e[k] = R(io.load(Q + k, off));
+            if constexpr (!kStash) pk_e[k] = R(io.load(Q + k, off));
             pk_n[k] = WN ? R(io.load(k, off)) : R(0);
         }
     };
     auto load_own_any = [&](int zc) {
-        if constexpr (kStash) {
-#pragma unroll
-            for (int k = 1; k < Q; ++k) {
-                pk_e[k] = R(sG[zc & 1][k - 1][tid]);
-                pk_n[k] = R(0);
-            }
-        } else if constexpr (NMODE == kTauOne) {
+        if constexpr (NMODE == kTauOne) {
             load_own(zc, std::false_type{});
         } else if constexpr (NMODE == kTauAny) {
             load_own(zc, std::true_type{});
@@ -372,7 +382,7 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         const int own = wrap_index(zc, g.nz) * nxy + oy * g.nx + ox;
 
         const double rho_d = o_rho[ZH], E_d = o_E[ZH];
-        const R rho = R(rho_d), E = R(E_d), T = sT[sc][oe];
+        const R rho = R(rho_d), E = R(E_d), T = sT[sc][of];
         const R p = o_p[ZH];
         const R inv_rho = R(1) / rho;
         const R ux = o_jx[ZH] * inv_rho, uy = o_jy[ZH] * inv_rho, uz = o_jz[ZH] * inv_rho;
@@ -382,8 +392,8 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         R div = R(0.5) * (sU[0][suc][of + 1] - sU[0][suc][of - 1]) +
                 R(0.5) * (sU[1][suc][of + FX] - sU[1][suc][of - FX]);
         if constexpr (D == 3) div += R(0.5) * (sU[2][sucp][of] - sU[2][sucm][of]);
-        const R dE = energy_source<D, R, EX>(p, div, rho, T, sRho[scm], sRho[sc], sRho[scp], sT[scm],
-                                             sT[sc], sT[scp], oe, cond_half, flags, ph, aux);
+        const R dE = energy_source<D, R, FX>(p, div, rho, T, sRho[scm], sRho[sc], sRho[scp], sT[scm],
+                                             sT[sc], sT[scp], of, cond_half, flags, ph, aux);
 
         NodeCollision<Q, S, R, WN> c;
         c.setup(rho, E, ux, uy, uz, Fo[0], Fo[1], Fo[2], inv_rho, dE, keepN, keepG, omega_E,
@@ -413,8 +423,13 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     const int zstart = dir > 0 ? z0 - ZH : z1 - 1 + ZH;
     S pn0[Q], pe0[Q];   // pulls of the first moment slot
     S held[kStash ? Q - 1 : 1];   // own node's energy pulls of plane zm, bound for the stash
+    // populations prefetched: both sets, or with the stash (which holds the energy pulls in
+    // registers until the collision) the density populations only
+    using Both = std::integral_constant<int, 3>;
+    using Ahead = std::integral_constant<int, kStash ? 1 : 3>;
+    using Late = std::integral_constant<int, kStash ? 2 : 0>;
     if constexpr (PIPE) {
-        if (m_e[0] >= 0) load_slot(zstart, 0, pn0, pe0);
+        if (m_e[0] >= 0) load_slot(zstart, 0, pn0, pe0, Ahead{});
     }
     for (int it = 0; it < niter; ++it) {
         const int zm = zstart + dir * it;   // moment stage; force at zm - dir, collision at zm - 2 dir
@@ -425,21 +440,22 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
 
         // ---------------- M: moments, EOS, Phi on the tile + 2-halo of plane zm
         if (m_e[0] >= 0) {
-            if constexpr (!PIPE) load_slot(zm, 0, pn0, pe0);
+            if constexpr (!PIPE) load_slot(zm, 0, pn0, pe0, Both{});
+            if constexpr (PIPE && Late::value != 0) load_slot(zm, 0, pn0, pe0, Late{});
             moments(0, pn0, pe0, sm, sj);
             if constexpr (kStash) {
 #pragma unroll
                 for (int k = 1; k < Q; ++k) held[k - 1] = pe0[k];
             }
             if constexpr (PIPE) {
-                if (it + 1 < niter) load_slot(zm + dir, 0, pn0, pe0);
+                if (it + 1 < niter) load_slot(zm + dir, 0, pn0, pe0, Ahead{});
             }
         }
 #pragma unroll
         for (int r = 1; r < ME; ++r) {
             if (m_e[r] < 0) continue;
             S pn[Q], pe[Q];
-            load_slot(zm, r, pn, pe);
+            load_slot(zm, r, pn, pe, Both{});
             moments(r, pn, pe, sm, sj);
         }
         __syncthreads();
@@ -456,11 +472,11 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
                 double fx, fy, fz;
                 force_at<Q, EX>(sPhi[sfm], sPhi[sf], sPhi[sfp], e, ph.A, ph.inv_alpha, fx, fy, fz);
                 const R Fx = R(fx), Fy = R(fy), Fz = R(fz);
-                const R inv_rho = R(1) / sRho[sf][e];
                 const int f = f_f[r];
-                sU[0][suf][f] = (sJ[0][sjf][e] + R(0.5) * Fx) * inv_rho;
-                sU[1][suf][f] = (sJ[1][sjf][e] + R(0.5) * Fy) * inv_rho;
-                sU[2][suf][f] = (sJ[2][sjf][e] + R(0.5) * Fz) * inv_rho;
+                const R inv_rho = R(1) / sRho[sf][f];
+                sU[0][suf][f] = (sJ[0][sjf][f] + R(0.5) * Fx) * inv_rho;
+                sU[1][suf][f] = (sJ[1][sjf][f] + R(0.5) * Fy) * inv_rho;
+                sU[2][suf][f] = (sJ[2][sjf][f] + R(0.5) * Fz) * inv_rho;
                 if (r == 0) {
                     fprev[0] = fcur[0]; fprev[1] = fcur[1]; fprev[2] = fcur[2];
                     fcur[0] = Fx; fcur[1] = Fy; fcur[2] = Fz;
@@ -470,8 +486,16 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         __syncthreads();
 
         // ---------------- C: energy source, collisions, store for plane zc = zm - dir ZH
+        if (collides) load_own_any(zc);
+        if constexpr (kStash) {
+            // plane zm takes the ring slot of plane zm - 2 dir, read just above by this same
+            // thread (every thread touches only its own column of the stash)
+            if (tid < NC) {
+#pragma unroll
+                for (int k = 1; k < Q; ++k) sG[zm & 1][k - 1][tid] = held[k - 1];
+            }
+        }
         if (collides) {
-            load_own_any(zc);
             if constexpr (NMODE == kTauOne) {
                 collide(zc, std::false_type{});
             } else if constexpr (NMODE == kTauAny) {
@@ -481,16 +505,11 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
                 else collide(zc, std::false_type{});
             }
         }
-        if constexpr (kStash) {
-            // plane zm takes the ring slot of plane zm - 2 dir, consumed just above by this
-            // same thread (every thread touches only its own column of the stash)
-            if (tid < NC) {
-#pragma unroll
-                for (int k = 1; k < Q; ++k) sG[zm & 1][k - 1][tid] = held[k - 1];
-            }
-        }
         if constexpr (!kFiveRing) __syncthreads();
     }
+    // A caller that runs several tiles in one workgroup reuses the LDS rings: the next tile's
+    // moment stage must not overwrite planes that a slower wave's last collision still reads.
+    if constexpr (kFiveRing) __syncthreads();
 }
 
 template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool BUF, int NMODE,
