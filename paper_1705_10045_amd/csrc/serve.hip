@@ -28,7 +28,7 @@
 namespace lbm {
 
 constexpr int kPoolTX = 32, kPoolTY = 16;  // tile of the FP32 D3Q19 step, one moment slot per
-constexpr int kPoolThreads = 768;          // thread (no prefetch: both collisions are compiled in)
+constexpr int kPoolThreads = 768;          // thread, LDS stash as in the single-simulation launch
 constexpr int kPoolChunk = 16;             // z planes per tile: uniform tile work in the mix
 constexpr int kPoolGrid = 256;             // persistent workgroups: one per compute unit
 constexpr int kPoolMaxEdge = 128;
@@ -54,6 +54,7 @@ __global__ void __launch_bounds__(kPoolThreads)
 k_pool_step(const SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ hdr,
             const double* __restrict__ table, double s0, double inv_ds, int* __restrict__ errs)
 {
+    __shared__ TileLds<19, float, float, kPoolTX, kPoolTY, true> lds;
     const int total = hdr->total_tiles;
     const int nslots = hdr->nslots;
     // XCD-aware order: each XCD walks contiguous runs of the work list, so neighbouring tiles
@@ -79,8 +80,14 @@ k_pool_step(const SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ h
         aux.tab_s0 = s0;
         aux.tab_inv_ds = inv_ds;
         aux.err = errs + lo;
-        step_tile<19, float, float, kPoolTX, kPoolTY, kPoolThreads, false, true, kTauRuntime, false>(
-            src, dst, g, ph, aux, local);
+        // each request's own collision: tau = 1 (with the density prefetch) or general; both
+        // share the workgroup's LDS
+        if (ph.omega == 1.0)
+            step_tile<19, float, float, kPoolTX, kPoolTY, kPoolThreads, true, true, kTauOne, true>(
+                lds, src, dst, g, ph, aux, local);
+        else
+            step_tile<19, float, float, kPoolTX, kPoolTY, kPoolThreads, false, true, kTauAny, true>(
+                lds, src, dst, g, ph, aux, local);
     }
 }
 

@@ -11,8 +11,8 @@
 //
 // Work decomposition: a workgroup owns a TX x TY column of nodes and marches through a chunk
 // of z planes (even chunks upward, odd chunks downward).  Per z iteration it runs three
-// stages, with a barrier after M and after F (and after C when the LDS rings are too short to
-// let the next iteration's M overlap it):
+// stages, with a barrier after M and after F (D3Q19's LDS rings are deep enough for the next
+// iteration's M to overlap C; D2Q9 also has a barrier after C):
 //   M: pull 2Q populations and form rho, j, E, T, p, Phi for plane zm on the tile plus a
 //      2-node halo (LDS rings; Phi is kept on the whole region, rho, T and j only on the tile
 //      plus a 1-node halo, the part that the force and the energy source read);
@@ -136,9 +136,41 @@ struct PopIO<float, true> {
 // How the collision treats the density populations: with tau = 1 the BGK term of N' no longer
 // depends on N_k (N' = Neq(rho, u + du) exactly), so they need not be re-read.
 enum NMode : int {
-    kTauOne = 0,     // caller guarantees tau = 1
-    kTauAny = 1,     // always re-read N_k
-    kTauRuntime = 2  // decide per call from the parameters
+    kTauOne = 0,  // caller guarantees tau = 1
+    kTauAny = 1   // re-read N_k
+};
+
+// LDS of one workgroup's tile: the rings of the three stages and the stash.  The caller owns it
+// (one __shared__ object per kernel), so kernels that run several instantiations of the tile
+// step share one allocation.
+template <int Q, class S, class R, int TX, int TY, bool STASH>
+struct TileLds {
+    static constexpr int D = Lattice<Q>::D;
+    static constexpr int NC = TX * TY;                           // tile
+    static constexpr int EX = TX + 4, EY = TY + 4, NE = EX * EY;   // tile + 2-halo
+    static constexpr int FX = TX + 2, FY = TY + 2, NF = FX * FY;   // tile + 1-halo
+    static constexpr bool kStash = STASH && D == 3;
+    // Planes held.  An iteration runs M(zm) | barrier | F(zm-1) | barrier | C(zm-2), and no
+    // barrier closes it, so the next iteration's M(zm+1) may overlap a slower wave's C(zm-2):
+    //   rho, T: C reads zm-3 .. zm-1 while M writes zm+1                 -> 5 planes
+    //   Phi:    F reads zm-2 .. zm; the next write follows a barrier      -> 3 planes
+    //   j:      F reads zm-1; M writes zm+1                              -> 2 planes
+    //   u*x,y:  F writes zf, C reads zf-1; the next F follows a barrier   -> 2 planes
+    //   u*z:    C reads zf-2 and zf                                      -> 3 planes
+    // D2Q9 has one plane of each and a barrier closing the iteration.
+    static constexpr int RING = (D == 3) ? 5 : 1;
+    static constexpr int PR = (D == 3) ? 3 : 1;
+    static constexpr int JR = (D == 3) ? 2 : 1;
+    static constexpr int UH = (D == 3) ? 2 : 1;
+    static constexpr int UZ = (D == 3) ? 3 : 1;
+
+    double phi[PR][NE];          // Phi on the tile + 2-halo
+    R rho[RING][NF];             // rho, T, j on the tile + 1-halo
+    R T[RING][NF];
+    R j[3][JR][NF];
+    R uh[2][UH][NF];             // u*x, u*y
+    R uz[UZ][NF];                // u*z
+    S g[kStash ? 2 : 1][kStash ? Q - 1 : 1][kStash ? NC : 1];   // stash: own energy pulls
 };
 
 // One workgroup's share of a step: tile `lb` (x fastest, then y, then z chunk) of the box
@@ -160,7 +192,8 @@ enum NMode : int {
 // energy pulls already occupy registers until the collision).
 template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool BUF, int NMODE,
           bool STASH>
-__device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restrict__ dst,
+__device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
+                                          const S* __restrict__ src, S* __restrict__ dst,
                                           const StepGeom& g, const Phys& ph, const StepAux& aux,
                                           const int lb)
 {
@@ -171,33 +204,31 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     constexpr int ZH = (D == 3) ? 2 : 0;    // lead of the moment stage over the collision
     constexpr int NC = TX * TY;             // collision threads
     static_assert(NTH >= NC && NTH % 64 == 0, "one collision node per thread");
-    constexpr int EX = TX + 4, EY = TY + 4, NE = EX * EY;   // moments: tile + 2-halo
-    constexpr int FX = TX + 2, FY = TY + 2, NF = FX * FY;   // force/u*: tile + 1-halo
-    constexpr bool kStash = STASH && D == 3;
-    // Planes of Phi, rho, T held: the collision reads zc-1 .. zc+1 while the moment stage writes
-    // zc+2; with a fifth plane, the next iteration's moment stage (zc+3) cannot overwrite what
-    // a slower wave's collision still reads, and the barrier that closes an iteration is not
-    // needed.
-    constexpr bool kFiveRing = D == 3;
-    constexpr int RING = (D == 3) ? (kFiveRing ? 5 : 4) : 1;
-    constexpr int JR = (D == 3) ? 2 : 1;    // planes of j held (zf, zf+1)
-    constexpr int UR = (D == 3) ? 3 : 1;    // planes of u* held (zc-1 .. zc+1)
+    using Lds = TileLds<Q, S, R, TX, TY, STASH>;
+    constexpr int EX = Lds::EX, EY = Lds::EY, NE = Lds::NE;
+    constexpr int FX = Lds::FX, NF = Lds::NF;
+    constexpr bool kStash = Lds::kStash;
+    constexpr bool kFiveRing = D == 3;   // no barrier closes an iteration
+    constexpr int RING = Lds::RING, PR = Lds::PR, JR = Lds::JR, UH = Lds::UH, UZ = Lds::UZ;
     // moment slots beyond the first NTH go to threads without collision work when they fit
     constexpr int EXTRA = NE > NTH ? NE - NTH : 0;
     constexpr bool SPARE = EXTRA > 0 && EXTRA <= NTH - NC;
     constexpr int ME = SPARE ? 2 : (NE + NTH - 1) / NTH;
     constexpr int MF = (NF + NTH - 1) / NTH;
 
-    __shared__ double sPhi[RING][NE];
-    __shared__ R sRho[RING][NF];
-    __shared__ R sT[RING][NF];
-    __shared__ R sJ[3][JR][NF];
-    __shared__ R sU[3][UR][NF];
-    __shared__ S sG[kStash ? 2 : 1][kStash ? Q - 1 : 1][kStash ? NC : 1];
+    auto& sPhi = lds.phi;
+    auto& sRho = lds.rho;
+    auto& sT = lds.T;
+    auto& sJ = lds.j;
+    auto& sUh = lds.uh;
+    auto& sUz = lds.uz;
+    auto& sG = lds.g;
 
     auto ring = [](int z) { return (z + 10) % RING; };        // z >= -10
+    auto pring = [](int z) { return (z + 9) % PR; };          // z >= -9
     auto jring = [](int z) { return (z + 4) & (JR - 1); };
-    auto uring = [](int z) { return (z + 6) % UR; };          // z >= -6
+    auto uhring = [](int z) { return (z + 6) & (UH - 1); };
+    auto uzring = [](int z) { return (z + 6) % UZ; };         // z >= -6
 
     const int tid = threadIdx.x;
     const int tix = lb % g.ntx;
@@ -263,7 +294,6 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
     const unsigned flags = ph.flags;
     const bool pseudo = (flags & kPseudo) != 0;
     // whether the collision re-reads the density populations (not needed with tau = 1)
-    const bool needN = NMODE == kTauAny || (NMODE == kTauRuntime && keepN != R(0));
 
     // register ring of the own node's moments: [0] newest plane ... [ZH] plane being collided
     // (T of that plane is read from its LDS ring)
@@ -302,8 +332,8 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         }
     };
 
-    // moments, EOS and Phi of moment slot r (plane in ring slots sm, sj)
-    auto moments = [&](int r, const S (&pn)[Q], const S (&pe)[Q], int sm, int sj) {
+    // moments, EOS and Phi of moment slot r (plane in ring slots sm, sp, sj)
+    auto moments = [&](int r, const S (&pn)[Q], const S (&pe)[Q], int sm, int sp, int sj) {
         double dr, djx, djy, djz, dE, dT, p, phi2;
         bool ok;
         moment_sums<Q>(pn, pe, dr, djx, djy, djz, dE);
@@ -312,7 +342,7 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             atomicOr(aux.err, 1);
             phi2 = 0.0;
         }
-        sPhi[sm][m_e[r]] = sqrt(phi2);
+        sPhi[sp][m_e[r]] = sqrt(phi2);
         const int f = m_f[r];
         if (f >= 0) {
             sRho[sm][f] = R(dr);
@@ -363,22 +393,13 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             pk_n[k] = WN ? R(io.load(k, off)) : R(0);
         }
     };
-    auto load_own_any = [&](int zc) {
-        if constexpr (NMODE == kTauOne) {
-            load_own(zc, std::false_type{});
-        } else if constexpr (NMODE == kTauAny) {
-            load_own(zc, std::true_type{});
-        } else {
-            if (needN) load_own(zc, std::true_type{});
-            else load_own(zc, std::false_type{});
-        }
-    };
+    using WithN = std::integral_constant<bool, NMODE == kTauAny>;
 
     // energy source and both collisions of the own node at plane zc; stores the result
     auto collide = [&](int zc, auto with_n) {
         constexpr bool WN = decltype(with_n)::value;
         const int sc = ring(zc), scm = ring(zc - 1), scp = ring(zc + 1);
-        const int suc = uring(zc), sucm = uring(zc - 1), sucp = uring(zc + 1);
+        const int suc = uhring(zc), sucm = uzring(zc - 1), sucp = uzring(zc + 1);
         const int own = wrap_index(zc, g.nz) * nxy + oy * g.nx + ox;
 
         const double rho_d = o_rho[ZH], E_d = o_E[ZH];
@@ -389,9 +410,9 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         const R* Fo = (ZH > 0) ? fprev : fcur;
 
         // div u* by central differences on each axis (section 6.2)
-        R div = R(0.5) * (sU[0][suc][of + 1] - sU[0][suc][of - 1]) +
-                R(0.5) * (sU[1][suc][of + FX] - sU[1][suc][of - FX]);
-        if constexpr (D == 3) div += R(0.5) * (sU[2][sucp][of] - sU[2][sucm][of]);
+        R div = R(0.5) * (sUh[0][suc][of + 1] - sUh[0][suc][of - 1]) +
+                R(0.5) * (sUh[1][suc][of + FX] - sUh[1][suc][of - FX]);
+        if constexpr (D == 3) div += R(0.5) * (sUz[sucp][of] - sUz[sucm][of]);
         const R dE = energy_source<D, R, FX>(p, div, rho, T, sRho[scm], sRho[sc], sRho[scp], sT[scm],
                                              sT[sc], sT[scp], of, cond_half, flags, ph, aux);
 
@@ -436,13 +457,14 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         const int zc = zm - dir * ZH;
         const bool collides = it >= 2 * ZH && own_in_xy;
         const int sm = ring(zm);
+        const int sp = pring(zm);
         const int sj = jring(zm);
 
         // ---------------- M: moments, EOS, Phi on the tile + 2-halo of plane zm
         if (m_e[0] >= 0) {
             if constexpr (!PIPE) load_slot(zm, 0, pn0, pe0, Both{});
             if constexpr (PIPE && Late::value != 0) load_slot(zm, 0, pn0, pe0, Late{});
-            moments(0, pn0, pe0, sm, sj);
+            moments(0, pn0, pe0, sm, sp, sj);
             if constexpr (kStash) {
 #pragma unroll
                 for (int k = 1; k < Q; ++k) held[k - 1] = pe0[k];
@@ -456,27 +478,27 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
             if (m_e[r] < 0) continue;
             S pn[Q], pe[Q];
             load_slot(zm, r, pn, pe, Both{});
-            moments(r, pn, pe, sm, sj);
+            moments(r, pn, pe, sm, sp, sj);
         }
         __syncthreads();
 
         // ---------------- F: force and u* on the tile + 1-halo of plane zf = zm - dir ZH/2
         if (it >= ZH) {
             const int zf = zm - dir * (ZH / 2);
-            const int sf = ring(zf), sfm = ring(zf - 1), sfp = ring(zf + 1);
-            const int sjf = jring(zf), suf = uring(zf);
+            const int sf = ring(zf), spf = pring(zf), spfm = pring(zf - 1), spfp = pring(zf + 1);
+            const int sjf = jring(zf), suhf = uhring(zf), suzf = uzring(zf);
 #pragma unroll
             for (int r = 0; r < MF; ++r) {
                 if (f_f[r] < 0) continue;
                 const int e = f_e[r];
                 double fx, fy, fz;
-                force_at<Q, EX>(sPhi[sfm], sPhi[sf], sPhi[sfp], e, ph.A, ph.inv_alpha, fx, fy, fz);
+                force_at<Q, EX>(sPhi[spfm], sPhi[spf], sPhi[spfp], e, ph.A, ph.inv_alpha, fx, fy, fz);
                 const R Fx = R(fx), Fy = R(fy), Fz = R(fz);
                 const int f = f_f[r];
                 const R inv_rho = R(1) / sRho[sf][f];
-                sU[0][suf][f] = (sJ[0][sjf][f] + R(0.5) * Fx) * inv_rho;
-                sU[1][suf][f] = (sJ[1][sjf][f] + R(0.5) * Fy) * inv_rho;
-                sU[2][suf][f] = (sJ[2][sjf][f] + R(0.5) * Fz) * inv_rho;
+                sUh[0][suhf][f] = (sJ[0][sjf][f] + R(0.5) * Fx) * inv_rho;
+                sUh[1][suhf][f] = (sJ[1][sjf][f] + R(0.5) * Fy) * inv_rho;
+                if constexpr (D == 3) sUz[suzf][f] = (sJ[2][sjf][f] + R(0.5) * Fz) * inv_rho;
                 if (r == 0) {
                     fprev[0] = fcur[0]; fprev[1] = fcur[1]; fprev[2] = fcur[2];
                     fcur[0] = Fx; fcur[1] = Fy; fcur[2] = Fz;
@@ -486,7 +508,7 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
         __syncthreads();
 
         // ---------------- C: energy source, collisions, store for plane zc = zm - dir ZH
-        if (collides) load_own_any(zc);
+        if (collides) load_own(zc, WithN{});
         if constexpr (kStash) {
             // plane zm takes the ring slot of plane zm - 2 dir, read just above by this same
             // thread (every thread touches only its own column of the stash)
@@ -495,16 +517,7 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restri
                 for (int k = 1; k < Q; ++k) sG[zm & 1][k - 1][tid] = held[k - 1];
             }
         }
-        if (collides) {
-            if constexpr (NMODE == kTauOne) {
-                collide(zc, std::false_type{});
-            } else if constexpr (NMODE == kTauAny) {
-                collide(zc, std::true_type{});
-            } else {
-                if (needN) collide(zc, std::true_type{});
-                else collide(zc, std::false_type{});
-            }
-        }
+        if (collides) collide(zc, WithN{});
         if constexpr (!kFiveRing) __syncthreads();
     }
     // A caller that runs several tiles in one workgroup reuses the LDS rings: the next tile's
@@ -518,8 +531,9 @@ __global__ void __launch_bounds__(NTH)
 k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const Phys ph,
        const StepAux aux)
 {
+    __shared__ TileLds<Q, S, R, TX, TY, STASH> lds;
     step_tile<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, STASH>(
-        src, dst, g, ph, aux, xcd_logical_block(blockIdx.x, gridDim.x));
+        lds, src, dst, g, ph, aux, xcd_logical_block(blockIdx.x, gridDim.x));
 }
 
 }  // namespace lbm
