@@ -11,7 +11,8 @@
 namespace lbm {
 
 // rho = sum N_k, j = sum c_k N_k, E = sum g_k (eq:hydro, section 4), summed in FP64 in direction
-// order (exact for FP32 populations up to the final rounding).
+// order (exact for FP32 populations up to the final rounding).  The density sums come first:
+// their populations may have been loaded earlier than the energy populations.
 template <int Q, class S>
 __device__ __forceinline__ void moment_sums(const S* pn, const S* pe, double& dr, double& djx,
                                             double& djy, double& djz, double& dE)
@@ -22,11 +23,12 @@ __device__ __forceinline__ void moment_sums(const S* pn, const S* pe, double& dr
     for (int k = 0; k < Q; ++k) {
         const double n = double(pn[k]);
         dr += n;
-        dE += double(pe[k]);
         if (L::cx[k] == 1) djx += n; else if (L::cx[k] == -1) djx -= n;
         if (L::cy[k] == 1) djy += n; else if (L::cy[k] == -1) djy -= n;
         if (L::cz[k] == 1) djz += n; else if (L::cz[k] == -1) djz -= n;
     }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) dE += double(pe[k]);
 }
 
 // T = E / (rho c_V), the van der Waals pressure (section 3) and Phi^2 = rho theta - p, FP64.

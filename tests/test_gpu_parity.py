@@ -238,15 +238,18 @@ def test_unstable_state_reported():
         assert e.value.status == lbm.LBM_EUNSTABLE
 
 
-@pytest.mark.parametrize("shape", [(21, 30, 45), (23, 18, 44)])
+@pytest.mark.parametrize("storage,shape", [(4, (21, 30, 45)), (4, (23, 18, 44)),
+                                           (8, (21, 30, 45))])
 @pytest.mark.parametrize("tau", [1.0, 0.8])
-def test_launch_variants_are_bitwise_identical(tau, shape):
-    """Every tile shape, thread count, z-chunk length and load order of the fused step computes
-    the same per-node arithmetic: results agree bit for bit (also a race check on the LDS
-    rings), for the tau = 1 collision and the general one, on odd and even box widths."""
+def test_launch_variants_are_bitwise_identical(tau, storage, shape):
+    """Every tile shape, thread count, z-chunk length, load order and LDS stash of the fused step
+    computes the same per-node arithmetic: results agree bit for bit (also a race check on the
+    LDS rings), for the tau = 1 collision and the general one, on odd and even box widths, with
+    FP32 and FP64 populations."""
     case = droplet(shape=shape, radius=6.0, tau=tau)
     ref = None
-    with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"]) as s:
+    with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"],
+                 storage_bytes=storage) as s:
         ck = s.checkpoint()
         v = 0
         while True:
