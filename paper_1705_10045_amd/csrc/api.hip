@@ -238,8 +238,8 @@ lbm_status validate_fields(const lbm_params& p, const double* rho0, const double
     return LBM_OK;
 }
 
-// Launch geometry: tiles of the selected variant, z chunks sized for >= ~1024 workgroups
-// unless a chunk length is given.
+// Launch geometry: tiles of the selected variant and z chunks sized so that one round of
+// workgroups fills the GPU, unless a chunk length is given.
 void choose_geometry(lbm_sim* s, int chunk_request)
 {
     const lbm_params& p = s->p;
@@ -253,8 +253,8 @@ void choose_geometry(lbm_sim* s, int chunk_request)
     int chunk = p.nz;
     if (p.lattice == 19) {
         // about as many workgroups as the 256 compute units hold at once (one round), with the
-        // longest z chunks that allows: each chunk pulls 5 halo planes and runs 4 warm-up
-        // iterations, so longer chunks waste less (chunks of at least 4 planes)
+        // longest z chunks that allows: each chunk runs the moment stage on 4 planes outside it
+        // (2 on each side), so longer chunks waste less (chunks of at least 4 planes)
         const long long cols = (long long)g.ntx * g.nty;
         const long long target = 256LL * per_cu;
         long long want = (target + cols - 1) / cols;
