@@ -22,6 +22,7 @@ Prints ONE JSON line:
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -39,11 +40,21 @@ KERNEL_SOURCES = ["paper_1705_10045_amd/csrc/step_kernel.hpp", "paper_1705_10045
                   "paper_1705_10045_amd/csrc/api.hip"]
 
 
-def kernel_source_hash():
+def _code_only(text):
+    """Source text without // and /* */ comments and trailing blanks: what the compiler sees."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
+def kernel_source_hash(read=None):
+    """Hash of the step kernel's code (comments excluded), stored beside counter readings so that
+    a reading taken on other code is not reported.  `read(rel)` returns a file's text (default:
+    the working tree)."""
+    read = read or (lambda rel: open(os.path.join(ROOT, rel)).read())
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        h.update(_code_only(read(rel)).encode())
     return h.hexdigest()[:16]
 
 
