@@ -23,6 +23,9 @@ PSEUDOFORCE = 8
 BAROTROPIC = 16
 ALL_TERMS = WORK | CONDUCTION | LATENT | PSEUDOFORCE
 
+WALL_T_BOTTOM = 1
+WALL_T_TOP = 2
+
 OK = 0
 EINVAL = -1
 EUNSTABLE = -3
@@ -35,6 +38,9 @@ class _Params(ctypes.Structure):
         ("rho_c", ctypes.c_double), ("T_c", ctypes.c_double), ("p_c", ctypes.c_double),
         ("c_v", ctypes.c_double), ("chi", ctypes.c_double), ("rhoQ", ctypes.c_double),
         ("T0_baro", ctypes.c_double), ("flags", ctypes.c_uint),
+        ("walls", ctypes.c_int), ("wall_heat", ctypes.c_uint),
+        ("T_bottom", ctypes.c_double), ("T_top", ctypes.c_double),
+        ("gravity", ctypes.c_double * 3),
     ]
 
 
@@ -56,6 +62,10 @@ def _lib():
         lib.orc_force.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double, _D, _D]
         lib.orc_divergence.argtypes = [ctypes.c_int] * 4 + [_D, _D]
         lib.orc_conduction.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double] * 2 + [_D, _D, _D]
+        lib.orc_force_walls.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, _D, _D]
+        lib.orc_divergence_walls.argtypes = [ctypes.c_int] * 3 + [_D, _D]
+        lib.orc_conduction_walls.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 2 + \
+            [_D, _D, ctypes.c_uint, ctypes.c_double, ctypes.c_double, _D]
         lib.orc_create.restype = ctypes.c_void_p
         lib.orc_create.argtypes = [ctypes.POINTER(_Params), _D, _D, _D,
                                    ctypes.POINTER(ctypes.c_int)]
@@ -137,12 +147,46 @@ def conduction(D, c_v, chi, rho, T):
     return out
 
 
+def force_walls(Phi, A):
+    """Force of section 3 on a D3Q19 box with walls normal to z (Phi mirrored beyond them)."""
+    Phi = _f64(Phi)
+    nz, ny, nx = Phi.shape
+    F = np.zeros((3,) + Phi.shape)
+    _lib().orc_force_walls(nx, ny, nz, float(A), _ptr(Phi), _ptr(F))
+    return F
+
+
+def divergence_walls(u):
+    """Central-difference divergence with walls normal to z (u_z mirrored with opposite sign)."""
+    u = _f64(u)
+    nz, ny, nx = u.shape[1:]
+    out = np.zeros(u.shape[1:])
+    _lib().orc_divergence_walls(nx, ny, nz, _ptr(u), _ptr(out))
+    return out
+
+
+def conduction_walls(c_v, chi, rho, T, wall_heat, T_bottom, T_top):
+    """Conduction increment with walls normal to z (adiabatic or held at T_bottom / T_top)."""
+    rho, T = _f64(rho), _f64(T)
+    nz, ny, nx = rho.shape
+    out = np.zeros(rho.shape)
+    _lib().orc_conduction_walls(nx, ny, nz, float(c_v), float(chi), _ptr(rho), _ptr(T),
+                                int(wall_heat), float(T_bottom), float(T_top), _ptr(out))
+    return out
+
+
 _PARAM_KEYS = ("tau", "tau_E", "A", "rho_c", "T_c", "p_c", "c_v", "chi", "rhoQ", "T0_baro",
                "flags")
 
 
+# walls, wall temperatures and the body force are optional keys of `params` (default: periodic
+# box, no body force)
+_WALL_DEFAULTS = {"walls": 0, "wall_heat": 0, "T_bottom": 0.0, "T_top": 0.0,
+                  "gravity": (0.0, 0.0, 0.0)}
+
+
 class Sim:
-    """One periodic simulation on the CPU in FP64."""
+    """One simulation on the CPU in FP64 (periodic, or with walls normal to z)."""
 
     def __init__(self, Q, params, rho0, u0, T0):
         rho0, u0, T0 = _f64(rho0), _f64(u0), _f64(T0)
@@ -152,6 +196,13 @@ class Sim:
         p = _Params(Q=Q, nx=nx, ny=ny, nz=nz)
         for k in _PARAM_KEYS:
             setattr(p, k, params[k] if k != "flags" else int(params[k]))
+        p.walls = int(params.get("walls", _WALL_DEFAULTS["walls"]))
+        p.wall_heat = int(params.get("wall_heat", _WALL_DEFAULTS["wall_heat"]))
+        p.T_bottom = float(params.get("T_bottom", _WALL_DEFAULTS["T_bottom"]))
+        p.T_top = float(params.get("T_top", _WALL_DEFAULTS["T_top"]))
+        gv = params.get("gravity", _WALL_DEFAULTS["gravity"])
+        for a in range(3):
+            p.gravity[a] = float(gv[a])
         self.Q, self.shape = Q, rho0.shape
         self._p = p
         st = ctypes.c_int()

@@ -18,6 +18,10 @@
  *   7. BGK collision + dg(1) + pseudoforce dg(2) of g_k               eq:gk, section 4
  *   8. streaming to x + c_k, periodic                                 eq:lbe, eq:gk
  *
+ * Walls and body force (not in the paper; readings listed in the design notes): optional
+ * no-slip walls normal to z halfway between planes (bounce-back of N and g in step 8; mirror
+ * ghosts beyond them in steps 3 and 5) and F += rho g in step 3.
+ *
  * Readings where the paper is not explicit (all listed in the design notes):
  *   - critical values rho_c, T_c, p_c are parameters in lattice units;
  *   - the multi-dimensional pressure work uses the central difference of
@@ -47,10 +51,20 @@
 typedef struct {
     int Q, D;
     int c[19][3];
+    int opp[19];       /* direction with c[opp[k]] = -c[k] */
     double w[19];
     double G[19];
     double alpha;
 } lattice;
+
+/* opp[k]: the direction with the opposite velocity, found by search */
+static void find_opposites(lattice* L)
+{
+    for (int k = 0; k < L->Q; ++k)
+        for (int m = 0; m < L->Q; ++m)
+            if (L->c[m][0] == -L->c[k][0] && L->c[m][1] == -L->c[k][1] && L->c[m][2] == -L->c[k][2])
+                L->opp[k] = m;
+}
 
 /* Velocity sets, weights (section 2) and force coefficients G_k, alpha (section 3).
  * Index 0 is the rest particle; then the nearest neighbours, then the next-nearest. */
@@ -69,6 +83,7 @@ static int make_lattice(int Q, lattice* L)
             else { L->w[k] = 1.0 / 36.0; L->G[k] = 0.25; }
         }
         L->alpha = 1.5;
+        find_opposites(L);
         return 2;
     }
     if (Q == 19) {
@@ -86,6 +101,7 @@ static int make_lattice(int Q, lattice* L)
             else { L->w[k] = 1.0 / 36.0; L->G[k] = 0.5; }
         }
         L->alpha = 3.0;
+        find_opposites(L);
         return 3;
     }
     return ORC_EINVAL;
@@ -221,10 +237,20 @@ static long node_at(int nx, int ny, int nz, long x, long y, long z)
     return wrap(x, nx) + (long)nx * (wrap(y, ny) + (long)ny * wrap(z, nz));
 }
 
+/* Plane index of z on a box with walls halfway below 0 and above nz - 1: a plane beyond a
+ * wall is the mirror image of the fluid plane on the other side of the wall. */
+static long mirror_z(long z, int nz)
+{
+    if (z < 0) return -1 - z;
+    if (z >= nz) return 2L * nz - 1 - z;
+    return z;
+}
+
 /* F(x) = (1/alpha h) [ A sum_k G_k Phi^2(x+e_k) e_k + (1-2A) Phi(x) sum_k G_k Phi(x+e_k) e_k ],
- * sums over the moving directions k = 1..b (section 3). */
+ * sums over the moving directions k = 1..b (section 3).  With walls, Phi beyond a wall is the
+ * mirror image (a wall that neither attracts nor repels the fluid more than the fluid itself). */
 static void force_field(const lattice* L, int nx, int ny, int nz, double A, const double* Phi,
-                        double* F)
+                        int walls, double* F)
 {
     const long n = (long)nx * ny * nz;
 #pragma omp parallel for schedule(static)
@@ -234,7 +260,9 @@ static void force_field(const lattice* L, int nx, int ny, int nz, double A, cons
                 long i = x + nx * (y + ny * z);
                 double s1[3] = {0, 0, 0}, s2[3] = {0, 0, 0};
                 for (int k = 1; k < L->Q; ++k) {
-                    long j = node_at(nx, ny, nz, x + L->c[k][0], y + L->c[k][1], z + L->c[k][2]);
+                    long zz = z + L->c[k][2];
+                    if (walls) zz = mirror_z(zz, nz);
+                    long j = node_at(nx, ny, nz, x + L->c[k][0], y + L->c[k][1], zz);
                     double ph = Phi[j];
                     for (int a = 0; a < 3; ++a) {
                         s1[a] += L->G[k] * ph * ph * L->c[k][a];
@@ -250,13 +278,22 @@ int orc_force(int Q, int nx, int ny, int nz, double A, const double* Phi, double
 {
     lattice L;
     if (make_lattice(Q, &L) < 0) return ORC_EINVAL;
-    force_field(&L, nx, ny, nz, A, Phi, F);
+    force_field(&L, nx, ny, nz, A, Phi, 0, F);
+    return ORC_OK;
+}
+
+int orc_force_walls(int nx, int ny, int nz, double A, const double* Phi, double* F)
+{
+    lattice L;
+    make_lattice(19, &L);
+    force_field(&L, nx, ny, nz, A, Phi, 1, F);
     return ORC_OK;
 }
 
 /* div u = sum_a (u_a(x + e_a) - u_a(x - e_a)) / 2h over the D spatial axes
- * (the central difference of section 6.2 on each axis). */
-static void divergence(int D, int nx, int ny, int nz, const double* u, double* div)
+ * (the central difference of section 6.2 on each axis).  With walls, u_z beyond a wall is the
+ * mirror image with the opposite sign, so the wall face carries no flux. */
+static void divergence(int D, int nx, int ny, int nz, const double* u, int walls, double* div)
 {
     const long n = (long)nx * ny * nz;
 #pragma omp parallel for schedule(static)
@@ -270,7 +307,10 @@ static void divergence(int D, int nx, int ny, int nz, const double* u, double* d
                     e[a] = 1;
                     long ip = node_at(nx, ny, nz, x + e[0], y + e[1], z + e[2]);
                     long im = node_at(nx, ny, nz, x - e[0], y - e[1], z - e[2]);
-                    d += (u[a * n + ip] - u[a * n + im]) / 2.0;
+                    double up = u[a * n + ip], um = u[a * n + im];
+                    if (walls && a == 2 && z == nz - 1) up = -u[a * n + i];
+                    if (walls && a == 2 && z == 0) um = -u[a * n + i];
+                    d += (up - um) / 2.0;
                 }
                 div[i] = d;
             }
@@ -279,15 +319,30 @@ static void divergence(int D, int nx, int ny, int nz, const double* u, double* d
 int orc_divergence(int D, int nx, int ny, int nz, const double* u, double* div)
 {
     if (D != 2 && D != 3) return ORC_EINVAL;
-    divergence(D, nx, ny, nz, u, div);
+    divergence(D, nx, ny, nz, u, 0, div);
     return ORC_OK;
 }
+
+int orc_divergence_walls(int nx, int ny, int nz, const double* u, double* div)
+{
+    divergence(3, nx, ny, nz, u, 1, div);
+    return ORC_OK;
+}
+
+/* Wall description for the conduction stencil: at a wall face the node beyond the wall has
+ * the mirrored density and either the mirrored temperature (adiabatic wall: no flux) or the
+ * temperature 2 T_wall - T(x), which puts T_wall on the wall face half a cell away. */
+typedef struct {
+    int on;
+    unsigned fixed;      /* ORC_WALL_T_BOTTOM | ORC_WALL_T_TOP */
+    double T_bottom, T_top;
+} walls_t;
 
 /* div(lambda grad T) with lambda = rho c_v chi (section 4), conservative form:
  * sum_a [ lam(x, x+e_a) (T(x+e_a) - T(x)) - lam(x, x-e_a) (T(x) - T(x-e_a)) ],
  * lam(x, y) = c_v chi (rho(x) + rho(y)) / 2. */
 static void conduction(int D, int nx, int ny, int nz, double c_v, double chi, const double* rho,
-                       const double* T, double* out)
+                       const double* T, const walls_t* wl, double* out)
 {
 #pragma omp parallel for schedule(static)
     for (long z = 0; z < nz; ++z)
@@ -300,9 +355,18 @@ static void conduction(int D, int nx, int ny, int nz, double c_v, double chi, co
                     e[a] = 1;
                     long ip = node_at(nx, ny, nz, x + e[0], y + e[1], z + e[2]);
                     long im = node_at(nx, ny, nz, x - e[0], y - e[1], z - e[2]);
-                    double lp = c_v * chi * (rho[i] + rho[ip]) / 2.0;
-                    double lm = c_v * chi * (rho[i] + rho[im]) / 2.0;
-                    s += lp * (T[ip] - T[i]) - lm * (T[i] - T[im]);
+                    double rp = rho[ip], rm = rho[im], Tp = T[ip], Tm = T[im];
+                    if (wl && wl->on && a == 2 && z == nz - 1) {
+                        rp = rho[i];
+                        Tp = (wl->fixed & ORC_WALL_T_TOP) ? 2.0 * wl->T_top - T[i] : T[i];
+                    }
+                    if (wl && wl->on && a == 2 && z == 0) {
+                        rm = rho[i];
+                        Tm = (wl->fixed & ORC_WALL_T_BOTTOM) ? 2.0 * wl->T_bottom - T[i] : T[i];
+                    }
+                    double lp = c_v * chi * (rho[i] + rp) / 2.0;
+                    double lm = c_v * chi * (rho[i] + rm) / 2.0;
+                    s += lp * (Tp - T[i]) - lm * (T[i] - Tm);
                 }
                 out[i] = s;
             }
@@ -312,7 +376,16 @@ int orc_conduction(int D, int nx, int ny, int nz, double c_v, double chi, const 
                    const double* T, double* out)
 {
     if (D != 2 && D != 3) return ORC_EINVAL;
-    conduction(D, nx, ny, nz, c_v, chi, rho, T, out);
+    conduction(D, nx, ny, nz, c_v, chi, rho, T, NULL, out);
+    return ORC_OK;
+}
+
+int orc_conduction_walls(int nx, int ny, int nz, double c_v, double chi, const double* rho,
+                         const double* T, unsigned wall_heat, double T_bottom, double T_top,
+                         double* out)
+{
+    const walls_t wl = {1, wall_heat, T_bottom, T_top};
+    conduction(3, nx, ny, nz, c_v, chi, rho, T, &wl, out);
     return ORC_OK;
 }
 
@@ -350,6 +423,16 @@ static int valid_params(const orc_params* p)
     int d = (p->nx > 1) + (p->ny > 1) + (p->Q == 19 && p->nz > 1);
     if (d < 1) d = 1;
     if ((p->flags & ORC_CONDUCTION) && !(p->chi < 0.5 / d)) return 0;
+    if (p->walls) {
+        if (p->walls != 1 || p->Q != 19 || p->nz < 2) return 0;
+        if ((p->wall_heat & ORC_WALL_T_BOTTOM) && !(p->T_bottom > 0.0)) return 0;
+        if ((p->wall_heat & ORC_WALL_T_TOP) && !(p->T_top > 0.0)) return 0;
+        /* a fixed-temperature wall face is half a cell away, which doubles its conductance:
+         * the explicit update of a node next to it stays positive for chi < 1/(2d + 1) */
+        if ((p->flags & ORC_CONDUCTION) && p->wall_heat && !(p->chi < 1.0 / (2 * d + 1))) return 0;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (!isfinite(p->gravity[a])) return 0;
     return 1;
 }
 
@@ -445,6 +528,15 @@ static int pass_eos(orc_sim* s)
     return ok;
 }
 
+/* Step 3 (continued): uniform body force, F += rho g. */
+static void pass_body_force(orc_sim* s)
+{
+    const long n = s->n;
+    for (int a = 0; a < 3; ++a)
+        if (s->p.gravity[a] != 0.0)
+            for (long i = 0; i < n; ++i) s->F[a * n + i] += s->rho[i] * s->p.gravity[a];
+}
+
 /* Step 4: du = F dt / rho (eq:edm); u* = u + du/2 (eq:ustar). */
 static void pass_velocity(orc_sim* s)
 {
@@ -464,9 +556,10 @@ static void pass_energy_source(orc_sim* s)
 {
     const orc_params* p = &s->p;
     const long n = s->n;
-    divergence(s->L.D, p->nx, p->ny, p->nz, s->us, s->divu);
+    divergence(s->L.D, p->nx, p->ny, p->nz, s->us, p->walls, s->divu);
+    const walls_t wl = {p->walls, p->wall_heat, p->T_bottom, p->T_top};
     if (p->flags & ORC_CONDUCTION)
-        conduction(s->L.D, p->nx, p->ny, p->nz, p->c_v, p->chi, s->rho, s->T, s->cond);
+        conduction(s->L.D, p->nx, p->ny, p->nz, p->c_v, p->chi, s->rho, s->T, &wl, s->cond);
     else
         memset(s->cond, 0, sizeof(double) * (size_t)n);
 #pragma omp parallel for schedule(dynamic, 256)
@@ -515,7 +608,9 @@ static void pass_collide(orc_sim* s)
     }
 }
 
-/* Step 8: N_k(x + c_k, t + 1) = N'_k(x, t), same for g_k; periodic. */
+/* Step 8: N_k(x + c_k, t + 1) = N'_k(x, t), same for g_k; periodic.  With walls, a population
+ * whose target lies beyond a wall returns to its own node in the opposite direction:
+ * N_{-k}(x, t + 1) = N'_k(x, t) (bounce-back, the wall halfway between the planes). */
 static void pass_stream(orc_sim* s)
 {
     const orc_params* p = &s->p;
@@ -526,8 +621,14 @@ static void pass_stream(orc_sim* s)
             for (long x = 0; x < p->nx; ++x) {
                 long i = x + p->nx * (y + p->ny * z);
                 for (int k = 0; k < Q; ++k) {
-                    long j = node_at(p->nx, p->ny, p->nz, x + s->L.c[k][0], y + s->L.c[k][1],
-                                     z + s->L.c[k][2]);
+                    const long zt = z + s->L.c[k][2];
+                    if (p->walls && (zt < 0 || zt >= p->nz)) {
+                        const int kb = s->L.opp[k];
+                        s->N[i * Q + kb] = s->Np[i * Q + k];
+                        s->g[i * Q + kb] = s->gp[i * Q + k];
+                        continue;
+                    }
+                    long j = node_at(p->nx, p->ny, p->nz, x + s->L.c[k][0], y + s->L.c[k][1], zt);
                     s->N[j * Q + k] = s->Np[i * Q + k];
                     s->g[j * Q + k] = s->gp[i * Q + k];
                 }
@@ -540,7 +641,8 @@ int orc_step(orc_sim* s, int nsteps)
     for (int t = 0; t < nsteps; ++t) {
         pass_moments(s);
         if (!pass_eos(s)) return ORC_EUNSTABLE;
-        force_field(&s->L, s->p.nx, s->p.ny, s->p.nz, s->p.A, s->Phi, s->F);
+        force_field(&s->L, s->p.nx, s->p.ny, s->p.nz, s->p.A, s->Phi, s->p.walls, s->F);
+        pass_body_force(s);
         pass_velocity(s);
         pass_energy_source(s);
         pass_collide(s);
@@ -555,7 +657,8 @@ int orc_moments(orc_sim* s, double* rho, double* ustar, double* E, double* T)
     const long n = s->n;
     pass_moments(s);
     int ok = pass_eos(s);
-    force_field(&s->L, s->p.nx, s->p.ny, s->p.nz, s->p.A, s->Phi, s->F);
+    force_field(&s->L, s->p.nx, s->p.ny, s->p.nz, s->p.A, s->Phi, s->p.walls, s->F);
+    pass_body_force(s);
     pass_velocity(s);
     if (rho) memcpy(rho, s->rho, sizeof(double) * (size_t)n);
     if (ustar) memcpy(ustar, s->us, sizeof(double) * (size_t)(3 * n));

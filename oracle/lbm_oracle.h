@@ -26,6 +26,10 @@ extern "C" {
 #define ORC_PSEUDOFORCE 8u   /* EDM "pseudoforces" on the energy populations         */
 #define ORC_BAROTROPIC 16u   /* EOS at the fixed temperature T0_baro (section 4)     */
 
+/* Walls (walls = 1): which walls are held at a fixed temperature; the others are adiabatic. */
+#define ORC_WALL_T_BOTTOM 1u /* z = -1/2 held at T_bottom                            */
+#define ORC_WALL_T_TOP    2u /* z = nz - 1/2 held at T_top                           */
+
 #define ORC_OK         0
 #define ORC_EINVAL    -1
 #define ORC_EUNSTABLE -3
@@ -39,6 +43,17 @@ typedef struct {
     double c_v, chi, rhoQ; /* specific heat, thermal diffusivity, rho_liq*Q   */
     double T0_baro;        /* EOS temperature when ORC_BAROTROPIC is set      */
     unsigned flags;
+    /* Solid walls normal to z (not part of the paper, which is periodic): walls = 1 puts
+     * no-slip walls halfway between lattice planes, below z = 0 and above z = nz - 1.  Streaming
+     * bounces populations back at them (N and g alike); beyond a wall Phi and rho are mirrored,
+     * u*_z is mirrored with the opposite sign, and T is mirrored (adiabatic wall) or set so that
+     * the wall face has the wall temperature (ORC_WALL_T_* in wall_heat).  D3Q19 only. */
+    int walls;
+    unsigned wall_heat;
+    double T_bottom, T_top;
+    /* Uniform body force per unit mass: F += rho g at every node (section 2, external force
+     * through the exact difference method). */
+    double gravity[3];
 } orc_params;
 
 /* Lattice tables: c[Q*3], w[Q], G[Q] (G[0] = 0), alpha.  Returns D or ORC_EINVAL. */
@@ -54,7 +69,8 @@ int orc_maxwell(double Tr, double* rv, double* rl, double* psat);
 /* Equilibrium populations (eq:feq) of a lattice at density rho and velocity u[3]. */
 int orc_equilibrium(int Q, double rho, const double* u, double* feq);
 
-/* Isotropic pseudopotential force of section 3 from a field Phi on a periodic box. */
+/* Isotropic pseudopotential force of section 3 from a field Phi on a periodic box (no walls,
+ * no body force). */
 int orc_force(int Q, int nx, int ny, int nz, double A, const double* Phi, double* F);
 
 /* Central-difference divergence of a vector field (3 planes) on a periodic box. */
@@ -64,6 +80,14 @@ int orc_divergence(int D, int nx, int ny, int nz, const double* u, double* div);
  * lambda = rho c_v chi, face conductivity = arithmetic mean of the two nodes. */
 int orc_conduction(int D, int nx, int ny, int nz, double c_v, double chi,
                    const double* rho, const double* T, double* out);
+
+/* The same three operators on a D3Q19 box with walls normal to z (mirror ghosts as described
+ * at orc_params.walls). */
+int orc_force_walls(int nx, int ny, int nz, double A, const double* Phi, double* F);
+int orc_divergence_walls(int nx, int ny, int nz, const double* u, double* div);
+int orc_conduction_walls(int nx, int ny, int nz, double c_v, double chi, const double* rho,
+                         const double* T, unsigned wall_heat, double T_bottom, double T_top,
+                         double* out);
 
 typedef struct orc_sim orc_sim;
 

@@ -218,6 +218,35 @@ def spinodal_3d(n=256, Tr=0.75, rho_mean=1.0, sigma=0.02, seed=SEED, params=None
                 T0=np.full(shape, Tr * p["T_c"]))
 
 
+def layer_distance(shape, height):
+    """Signed distance to the top of a layer filling the planes z < height above a wall at
+    z = -1/2 (negative inside the layer)."""
+    z = _grid(shape)[2]
+    return z - (height - 0.5)
+
+
+WALL_T_BOTTOM = 1
+WALL_T_TOP = 2
+
+
+def pool_boiling_3d(n=512, fill=0.6, Tr=0.8, T_bottom_r=0.9, T_top_r=0.7, gravity=1e-5,
+                    noise=0.01, seed=SEED, params=None, shape=None):
+    """D3Q19 pool boiling: walls normal to z (bottom held at T_bottom_r T_c, above the
+    saturation temperature of the layer; top held at T_top_r T_c), gravity along -z, a liquid
+    layer filling the lower `fill` of the box under its vapour at the coexistence densities of
+    Tr, +-noise uniform density noise, temperature Tr T_c, at rest."""
+    shape = tuple(shape) if shape is not None else (n, n, n)
+    p = dict(params or physics())
+    p.update(walls=1, wall_heat=WALL_T_BOTTOM | WALL_T_TOP, T_bottom=T_bottom_r * p["T_c"],
+             T_top=T_top_r * p["T_c"], gravity=(0.0, 0.0, -gravity))
+    rv, rl = coexistence(Tr)
+    rho = two_phase_smooth(layer_distance(shape, fill * shape[0]), rl * p["rho_c"],
+                           rv * p["rho_c"])
+    rho = with_uniform_noise(rho, seed, noise)
+    return dict(Q=19, params=p, rho0=rho, u0=uniform_velocity(shape, (0, 0, 0)),
+                T0=np.full(shape, Tr * p["T_c"]))
+
+
 SERVING_EDGES = (32, 48, 64, 96, 128)
 
 
