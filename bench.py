@@ -80,6 +80,16 @@ def workload(name):
                          "shape": [512, 512, 512], "storage": "fp32", "T_over_Tc": 0.75,
                          "rho_mean": 1.0, "noise_sigma": 0.02,
                          "terms": "work+conduction+latent+pseudoforces"}
+    if name in ("poolboil512", "poolboil128"):
+        n = 512 if name == "poolboil512" else 128
+        case = I.pool_boiling_3d(n=n)
+        pp = case["params"]
+        return case, 4, {"workload": "d3q19_pool_boiling_%d^3_fp32" % n, "lattice": "D3Q19",
+                         "shape": [n, n, n], "storage": "fp32", "T_over_Tc": 0.8,
+                         "walls": "z, bounce-back", "T_bottom_over_Tc": pp["T_bottom"] / pp["T_c"],
+                         "T_top_over_Tc": pp["T_top"] / pp["T_c"], "gravity": list(pp["gravity"]),
+                         "liquid_fill": 0.6, "noise": 0.01,
+                         "terms": "work+conduction+latent+pseudoforces"}
     raise SystemExit("unknown workload %s" % name)
 
 

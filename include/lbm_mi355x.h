@@ -39,6 +39,12 @@ typedef enum {
     LBM_EBUSY = -5       /* serving pool: no free slot or memory budget for the request   */
 } lbm_status;
 
+/* Walls held at a fixed temperature (lbm_params.wall_heat); the others are adiabatic. */
+enum {
+    LBM_WALL_T_BOTTOM = 1u,  /* wall below z = 0 held at T_bottom                            */
+    LBM_WALL_T_TOP = 2u      /* wall above z = nz - 1 held at T_top                          */
+};
+
 /* Physical terms (the ablations of sections 4-6). */
 enum {
     LBM_WORK = 1u,         /* pressure work -p div u*                                      */
@@ -60,6 +66,22 @@ typedef struct {
     double rhoQ;          /* rho_liq * Q, energy per volume released across the band         */
     double T0_baro;       /* EOS temperature with LBM_BAROTROPIC                             */
     unsigned flags;       /* LBM_WORK | LBM_CONDUCTION | LBM_LATENT | LBM_PSEUDOFORCE [...]  */
+    /* Solid walls for pool boiling.  The paper's boxes are periodic, so this is an extension
+     * with its own conventions (D3Q19 only).  walls = 1 puts no-slip walls normal to z halfway
+     * between lattice planes, below z = 0 and above z = nz - 1:
+     *   - streaming bounces N_k and g_k back at them (a population pulled from beyond a wall
+     *     is the opposite population leaving the node itself);
+     *   - beyond a wall, Phi and rho are mirrored and u*_z is mirrored with the opposite sign
+     *     (no flux through the wall face);
+     *   - T is mirrored (adiabatic wall) or set to 2 T_wall - T, which holds the wall face at
+     *     T_wall (LBM_WALL_T_* in wall_heat).
+     * walls = 0: periodic in z; wall_heat, T_bottom and T_top are then ignored. */
+    int walls;
+    unsigned wall_heat;
+    double T_bottom, T_top;
+    /* Uniform body force per unit mass (gravity): F += rho g at every node, applied by the
+     * exact difference method like the interparticle force (eq:edm).  Zero for none. */
+    double gravity[3];
 } lbm_params;
 
 typedef struct lbm_sim lbm_sim;
@@ -68,7 +90,10 @@ typedef struct lbm_sim lbm_sim;
  * g_k = geq_k(rho0 c_v T0, u0) (eq:feq with E in place of rho, section 4).
  * rho0[n], u0[3n], T0[n]: host FP64 fields.  stream: a hipStream_t on the current device on
  * which every later call enqueues its work, or NULL for a library-created stream.
- * Rejects (LBM_EINVAL) tau or tau_E <= 1/2, lattice/shape mismatch, a box whose population
+ * Rejects (LBM_EINVAL) tau or tau_E <= 1/2, lattice/shape mismatch, walls other than 0 or 1,
+ * walls with D2Q9 or with nz < 2, a held wall temperature that is not positive, chi >=
+ * 1/(2d + 1) with conduction and a held wall (its face is half a cell away), a non-finite
+ * gravity, a box whose population
  * plane (nx*ny*nz values) would exceed 4 GB (beyond any state that fits in HBM), chi >= 0.5/d with
  * conduction on (d = number of axes with extent > 1; section 6.1), a non-positive or
  * non-finite field, rho0/rho_c >= 3, Phi^2 = rho theta - p <= 0 at any node (section 3), and
@@ -99,8 +124,11 @@ lbm_status lbm_moments_device(lbm_sim* sim, double* rho, double* u_star, double*
 
 /* Totals of the current state accumulated in FP64 with a deterministic reduction order:
  * out[0] = sum N_k (mass), out[1..3] = sum c_k N_k (momentum), out[4] = sum g_k (internal
- * energy).  Mass and momentum are conserved by the step (eq:edm and the antisymmetric force);
- * energy is conserved when work and latent heat are off. */
+ * energy), over the stored post-collision populations.  Mass and momentum are conserved by the
+ * step on a periodic box without gravity (eq:edm and the antisymmetric force); energy is
+ * conserved when work and latent heat are off.  With walls, mass is conserved; the momentum is
+ * that of the populations before they bounce back, and the walls exchange energy and
+ * momentum. */
 lbm_status lbm_reduce(lbm_sim* sim, double out[5]);
 
 /* Number of time steps taken since lbm_init (or restored by lbm_restore). */
@@ -159,7 +187,7 @@ lbm_status lbm_coexistence(double Tr, double* rho_v, double* rho_l);
 typedef struct lbm_pool lbm_pool;
 
 /* Create a pool on the current device.  params of submitted requests must use lattice 19,
- * storage 4 and edges up to max_edge. */
+ * storage 4, edges up to max_edge, no walls and no gravity. */
 lbm_status lbm_pool_create(size_t hbm_budget_bytes, int max_slots, int steps_per_run,
                            void* stream, lbm_pool** out);
 

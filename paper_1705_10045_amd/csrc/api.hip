@@ -164,6 +164,11 @@ Phys make_phys(const lbm_params& p)
     ph.rhoQ = p.rhoQ;
     ph.T0_baro = p.T0_baro;
     ph.flags = p.flags;
+    ph.walls = p.walls;
+    ph.wall_heat = p.walls ? p.wall_heat : 0u;
+    ph.T_bottom = p.T_bottom;
+    ph.T_top = p.T_top;
+    for (int a = 0; a < 3; ++a) ph.g[a] = p.gravity[a];
     return ph;
 }
 
@@ -198,6 +203,24 @@ lbm_status validate_params(const lbm_params* p)
         return LBM_EINVAL;
     }
     if ((p->flags & LBM_BAROTROPIC) && !(p->T0_baro > 0)) { set_error("barotropic EOS needs T0_baro > 0"); return LBM_EINVAL; }
+    if (p->walls != 0 && p->walls != 1) { set_error("walls must be 0 (periodic) or 1, got %d", p->walls); return LBM_EINVAL; }
+    if (p->walls) {
+        if (p->lattice != 19 || p->nz < 2) { set_error("walls need D3Q19 and nz >= 2"); return LBM_EINVAL; }
+        if (((p->wall_heat & LBM_WALL_T_BOTTOM) && !(p->T_bottom > 0 && std::isfinite(p->T_bottom))) ||
+            ((p->wall_heat & LBM_WALL_T_TOP) && !(p->T_top > 0 && std::isfinite(p->T_top)))) {
+            set_error("a held wall temperature must be positive and finite");
+            return LBM_EINVAL;
+        }
+        // a held wall face is half a cell from the node next to it, which doubles its conductance
+        const double lim = 1.0 / (2 * (d < 1 ? 1 : d) + 1);
+        if ((p->flags & LBM_CONDUCTION) && (p->wall_heat & (LBM_WALL_T_BOTTOM | LBM_WALL_T_TOP)) &&
+            !(p->chi < lim)) {
+            set_error("conduction next to a held wall needs chi < 1/(2d + 1) = %g", lim);
+            return LBM_EINVAL;
+        }
+    }
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(p->gravity[a])) { set_error("gravity must be finite"); return LBM_EINVAL; }
     // the step addresses nodes within one population plane with 32-bit byte offsets
     const long long n = (long long)p->nx * p->ny * p->nz;
     if ((unsigned long long)padded_plane(n) * (unsigned long long)p->storage_bytes >= (1ull << 32)) {
@@ -412,7 +435,7 @@ lbm_status lbm_init(const lbm_params* params, const double* rho0, const double* 
     if (e == hipSuccess) e = hipMemcpyAsync(d_fields + 4 * s->n, T0, sizeof(double) * s->n, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
         e = launch_init(s->p.lattice, s->p.storage_bytes, s->buf[0], d_fields, d_fields + s->n, d_fields + 4 * s->n,
-                        s->p.nx, s->p.ny, s->p.nz, s->plane, s->p.c_v, s->stream);
+                        s->p.nx, s->p.ny, s->p.nz, s->plane, s->p.c_v, s->p.walls, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     (void)hipFree(d_fields);
     if (e != hipSuccess) { lbm_status r = hip_fail(e, "initial state"); lbm_free(s); return r; }

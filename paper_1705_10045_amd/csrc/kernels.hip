@@ -28,7 +28,7 @@ __device__ __forceinline__ long long node_index(int x, int y, int z, int nx, int
 template <int Q, class S>
 __global__ void k_init(S* __restrict__ buf, const double* __restrict__ rho0,
                        const double* __restrict__ u0, const double* __restrict__ T0, int nx,
-                       int ny, int nz, long long plane, double c_v)
+                       int ny, int nz, long long plane, double c_v, int walls)
 {
     using L = Lattice<Q>;
     const long long n = (long long)nx * ny * nz;
@@ -38,12 +38,19 @@ __global__ void k_init(S* __restrict__ buf, const double* __restrict__ rho0,
     node_xyz(i, nx, ny, x, y, z);
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-        const long long j = node_index(x + L::cx[k], y + L::cy[k], z + L::cz[k], nx, ny, nz);
+        // population k stored at node i is pulled by node i + c_k; toward a wall, it is pulled
+        // back by node i itself as the opposite direction
+        long long j = node_index(x + L::cx[k], y + L::cy[k], z + L::cz[k], nx, ny, nz);
+        int kd = k;
+        if (walls && (z + L::cz[k] < 0 || z + L::cz[k] >= nz)) {
+            j = i;
+            kd = opposite<Q>(k);
+        }
         const double rho = rho0[j];
         const double ux = u0[j], uy = u0[n + j], uz = u0[2 * n + j];
         const double E = rho * c_v * T0[j];
-        const double cu = L::cx[k] * ux + L::cy[k] * uy + L::cz[k] * uz;
-        const double P = eq_poly(weight<Q>(k), cu, ux * ux + uy * uy + uz * uz);
+        const double cu = L::cx[kd] * ux + L::cy[kd] * uy + L::cz[kd] * uz;
+        const double P = eq_poly(weight<Q>(kd), cu, ux * ux + uy * uy + uz * uz);
         buf[(long long)k * plane + i] = S(rho * P);
         buf[(long long)(Q + k) * plane + i] = S(E * P);
     }
@@ -63,13 +70,18 @@ __global__ void k_moments_a(const S* __restrict__ buf, double* __restrict__ scr,
     double rho = 0, jx = 0, jy = 0, jz = 0, E = 0;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-        const long long j = node_index(x - L::cx[k], y - L::cy[k], z - L::cz[k], nx, ny, nz);
-        const double nk = double(buf[(long long)k * plane + j]);
+        long long j = node_index(x - L::cx[k], y - L::cy[k], z - L::cz[k], nx, ny, nz);
+        int pk = k;
+        if (ph.walls && (z - L::cz[k] < 0 || z - L::cz[k] >= nz)) {   // bounce-back at a wall
+            pk = opposite<Q>(k);
+            j = i;
+        }
+        const double nk = double(buf[(long long)pk * plane + j]);
         rho += nk;
         jx += L::cx[k] * nk;
         jy += L::cy[k] * nk;
         jz += L::cz[k] * nk;
-        E += double(buf[(long long)(Q + k) * plane + j]);
+        E += double(buf[(long long)(Q + pk) * plane + j]);
     }
     const double T = E / (rho * ph.c_v);
     const double Te = (ph.flags & kBaro) ? ph.T0_baro : T;
@@ -87,8 +99,9 @@ __global__ void k_moments_a(const S* __restrict__ buf, double* __restrict__ scr,
     scr[6 * n + i] = sqrt(phi2);
 }
 
-// u* = (j + F/2)/rho (eq:ustar) with the force of section 3 from the Phi field; writes the
-// requested output fields (any pointer may be null).
+// u* = (j + F/2)/rho (eq:ustar) with the force of section 3 from the Phi field (mirrored beyond
+// walls) plus the body force rho g; writes the requested output fields (any pointer may be
+// null).
 template <int Q>
 __global__ void k_moments_b(const double* __restrict__ scr, int nx, int ny, int nz, Phys ph,
                             double* __restrict__ rho_o, double* __restrict__ us_o,
@@ -104,7 +117,9 @@ __global__ void k_moments_b(const double* __restrict__ scr, int nx, int ny, int 
     double s1[3] = {0, 0, 0}, s2[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
-        const double p = Phi[node_index(x + L::cx[k], y + L::cy[k], z + L::cz[k], nx, ny, nz)];
+        int zz = z + L::cz[k];
+        if (ph.walls) zz = zz < 0 ? -1 - zz : (zz >= nz ? 2 * nz - 1 - zz : zz);
+        const double p = Phi[node_index(x + L::cx[k], y + L::cy[k], zz, nx, ny, nz)];
         const double G = force_coef<Q>(k);
         s1[0] += G * p * p * L::cx[k]; s1[1] += G * p * p * L::cy[k]; s1[2] += G * p * p * L::cz[k];
         s2[0] += G * p * L::cx[k]; s2[1] += G * p * L::cy[k]; s2[2] += G * p * L::cz[k];
@@ -115,7 +130,8 @@ __global__ void k_moments_b(const double* __restrict__ scr, int nx, int ny, int 
     if (T_o) T_o[i] = scr[5 * n + i];
     if (us_o) {
         for (int a = 0; a < 3; ++a) {
-            const double F = (ph.A * s1[a] + (1.0 - 2.0 * ph.A) * Phi[i] * s2[a]) * ph.inv_alpha;
+            const double F = (ph.A * s1[a] + (1.0 - 2.0 * ph.A) * Phi[i] * s2[a]) * ph.inv_alpha +
+                             rho * ph.g[a];
             us_o[a * n + i] = (scr[(1 + a) * n + i] + 0.5 * F) / rho;
         }
     }
@@ -185,14 +201,21 @@ inline bool fits_buffer(const StepGeom& g, int Q, int storage_bytes)
     return (unsigned long long)g.plane * 2ull * Q * storage_bytes < (1ull << 32);
 }
 
+// The periodic instantiation, or the one with walls and body force when the parameters ask
+// for them.
 template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool STASH, bool BUF,
           int NMODE>
 hipError_t launch_one(const void* src, void* dst, const StepGeom& g, const Phys& ph,
                       const StepAux& aux, hipStream_t st)
 {
     const unsigned nblk = (unsigned)(g.ntx * g.nty * g.nchunks);
-    hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, STASH>), dim3(nblk),
-                       dim3(NTH), 0, st, (const S*)src, (S*)dst, g, ph, aux);
+    const bool ext = ph.walls || ph.g[0] != 0.0 || ph.g[1] != 0.0 || ph.g[2] != 0.0;
+    if (ext)
+        hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, STASH, true>),
+                           dim3(nblk), dim3(NTH), 0, st, (const S*)src, (S*)dst, g, ph, aux);
+    else
+        hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, STASH, false>),
+                           dim3(nblk), dim3(NTH), 0, st, (const S*)src, (S*)dst, g, ph, aux);
     return hipGetLastError();
 }
 
@@ -296,14 +319,14 @@ hipError_t launch_step(int Q, int storage_bytes, int variant, const void* src, v
 
 hipError_t launch_init(int Q, int storage_bytes, void* buf, const double* rho0, const double* u0,
                        const double* T0, int nx, int ny, int nz, long long plane, double c_v,
-                       hipStream_t st)
+                       int walls, hipStream_t st)
 {
     const long long n = (long long)nx * ny * nz;
     const dim3 grid(blocks_for(n, 256)), block(256);
-    if (Q == 19 && storage_bytes == 4) hipLaunchKernelGGL((k_init<19, float>), grid, block, 0, st, (float*)buf, rho0, u0, T0, nx, ny, nz, plane, c_v);
-    else if (Q == 19 && storage_bytes == 8) hipLaunchKernelGGL((k_init<19, double>), grid, block, 0, st, (double*)buf, rho0, u0, T0, nx, ny, nz, plane, c_v);
-    else if (Q == 9 && storage_bytes == 4) hipLaunchKernelGGL((k_init<9, float>), grid, block, 0, st, (float*)buf, rho0, u0, T0, nx, ny, nz, plane, c_v);
-    else if (Q == 9 && storage_bytes == 8) hipLaunchKernelGGL((k_init<9, double>), grid, block, 0, st, (double*)buf, rho0, u0, T0, nx, ny, nz, plane, c_v);
+    if (Q == 19 && storage_bytes == 4) hipLaunchKernelGGL((k_init<19, float>), grid, block, 0, st, (float*)buf, rho0, u0, T0, nx, ny, nz, plane, c_v, walls);
+    else if (Q == 19 && storage_bytes == 8) hipLaunchKernelGGL((k_init<19, double>), grid, block, 0, st, (double*)buf, rho0, u0, T0, nx, ny, nz, plane, c_v, walls);
+    else if (Q == 9 && storage_bytes == 4) hipLaunchKernelGGL((k_init<9, float>), grid, block, 0, st, (float*)buf, rho0, u0, T0, nx, ny, nz, plane, c_v, 0);
+    else if (Q == 9 && storage_bytes == 8) hipLaunchKernelGGL((k_init<9, double>), grid, block, 0, st, (double*)buf, rho0, u0, T0, nx, ny, nz, plane, c_v, 0);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

@@ -29,7 +29,7 @@ hipError_t launch_step(int Q, int storage_bytes, int variant, const void* src, v
                        const StepGeom& g, const Phys& ph, const StepAux& aux, hipStream_t st);
 hipError_t launch_init(int Q, int storage_bytes, void* buf, const double* rho0, const double* u0,
                        const double* T0, int nx, int ny, int nz, long long plane, double c_v,
-                       hipStream_t st);
+                       int walls, hipStream_t st);
 hipError_t launch_moments(int Q, int storage_bytes, const void* buf, double* scratch, int nx, int ny,
                           int nz, long long plane, const Phys& ph, int* err, double* rho,
                           double* us, double* E, double* T, hipStream_t st);

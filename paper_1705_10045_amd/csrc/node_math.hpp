@@ -76,13 +76,12 @@ __device__ __forceinline__ void force_at(const double* pm, const double* p0, con
 
 // Energy source dE of sections 4-6 at index e of planes of row width W: pressure work
 // -p div u*, conservative conduction with face conductivity c_V chi (rho_i + rho_j)/2, and the
-// latent-heat term inside the coexistence band.  rm/r0/rp and tm/t0/tp are the rho and T planes
-// at z - 1, z, z + 1.
+// latent-heat term inside the coexistence band.  r0 and t0 are the rho and T planes of the
+// node; rm, tm and rp, tp the values of its neighbours at z - 1 and z + 1 (D = 3).
 template <int D, class R, int W>
-__device__ __forceinline__ R energy_source(R p, R div, R rho, R T, const R* rm, const R* r0,
-                                           const R* rp, const R* tm, const R* t0, const R* tp,
-                                           int e, R cond_half, unsigned flags, const Phys& ph,
-                                           const StepAux& aux)
+__device__ __forceinline__ R energy_source(R p, R div, R rho, R T, R rm, const R* r0, R rp,
+                                           R tm, const R* t0, R tp, int e, R cond_half,
+                                           unsigned flags, const Phys& ph, const StepAux& aux)
 {
     R dE = R(0);
     if (flags & kWork) dE -= p * div;
@@ -91,7 +90,7 @@ __device__ __forceinline__ R energy_source(R p, R div, R rho, R T, const R* rm, 
         R acc = (rho + r0[e + 1]) * (t0[e + 1] - Tc) - (rho + r0[e - 1]) * (Tc - t0[e - 1]) +
                 (rho + r0[e + W]) * (t0[e + W] - Tc) - (rho + r0[e - W]) * (Tc - t0[e - W]);
         if constexpr (D == 3)
-            acc += (rho + rp[e]) * (tp[e] - Tc) - (rho + rm[e]) * (Tc - tm[e]);
+            acc += (rho + rp) * (tp - Tc) - (rho + rm) * (Tc - tm);
         dE += cond_half * acc;
     }
     if (flags & kLatent) {

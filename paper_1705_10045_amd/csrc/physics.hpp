@@ -22,7 +22,13 @@ struct Phys {
     double rhoQ;
     double T0_baro;
     unsigned flags;
+    int walls;                    // 1: no-slip walls normal to z below z = 0 and above nz - 1
+    unsigned wall_heat;           // kWallTBottom | kWallTTop: wall faces held at a temperature
+    double T_bottom, T_top;
+    double g[3];                  // body force per unit mass
 };
+
+enum : unsigned { kWallTBottom = 1u, kWallTTop = 2u };
 
 enum : unsigned { kWork = 1u, kConduction = 2u, kLatent = 4u, kPseudo = 8u, kBaro = 16u };
 

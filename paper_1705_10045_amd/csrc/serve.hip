@@ -83,10 +83,10 @@ k_pool_step(const SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ h
         // each request's own collision: tau = 1 (with the density prefetch) or general; both
         // share the workgroup's LDS
         if (ph.omega == 1.0)
-            step_tile<19, float, float, kPoolTX, kPoolTY, kPoolThreads, true, true, kTauOne, true>(
+            step_tile<19, float, float, kPoolTX, kPoolTY, kPoolThreads, true, true, kTauOne, true, false>(
                 lds, src, dst, g, ph, aux, local);
         else
-            step_tile<19, float, float, kPoolTX, kPoolTY, kPoolThreads, false, true, kTauAny, true>(
+            step_tile<19, float, float, kPoolTX, kPoolTY, kPoolThreads, false, true, kTauAny, true, false>(
                 lds, src, dst, g, ph, aux, local);
     }
 }
@@ -314,6 +314,11 @@ lbm_status lbm_pool_submit(lbm_pool* p, const lbm_params* params, const double* 
         set_error("pool requests must be D3Q19, FP32 storage, edges <= %d", kPoolMaxEdge);
         return LBM_EINVAL;
     }
+    if (params->walls || params->gravity[0] != 0.0 || params->gravity[1] != 0.0 ||
+        params->gravity[2] != 0.0) {
+        set_error("pool requests are periodic boxes without gravity");
+        return LBM_EINVAL;
+    }
     st = validate_fields(*params, rho0, u0, T0);
     if (st != LBM_OK) return st;
     int slot = -1;
@@ -352,7 +357,7 @@ lbm_status lbm_pool_submit(lbm_pool* p, const lbm_params* params, const double* 
     if (e == hipSuccess) e = hipMemcpyAsync(p->d_staging + 4 * n, T0, sizeof(double) * n, hipMemcpyHostToDevice, p->stream);
     if (e == hipSuccess)
         e = launch_init(19, 4, d.buf[0], p->d_staging, p->d_staging + n, p->d_staging + 4 * n, params->nx,
-                        params->ny, params->nz, d.geom.plane, params->c_v, p->stream);
+                        params->ny, params->nz, d.geom.plane, params->c_v, 0, p->stream);
     // the staging buffer is reused by the next submission: wait for this upload
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) {

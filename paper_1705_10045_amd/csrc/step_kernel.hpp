@@ -183,6 +183,10 @@ struct TileLds {
 // thread's first moment and force slots are its own collision node and the own node's
 // moments and force stay in registers between the stages.
 //
+// EXT: walls normal to z (Phys::walls: bounce-back pulls next to them, no stages on the planes
+// beyond them, mirror values for the stages next to them) and the body force rho g; the
+// instantiation without EXT is the periodic step with none of that code.
+//
 // PIPE: the pulls of the next plane's first moment slot are issued right after the current
 // plane's sums, so they are in flight during the force and collision stages.  STASH (D3Q19):
 // the collision does not pull its energy populations again; the moment stage already pulled
@@ -191,7 +195,7 @@ struct TileLds {
 // moves it there).  With the stash, the prefetch covers the density populations only (the
 // energy pulls already occupy registers until the collision).
 template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool BUF, int NMODE,
-          bool STASH>
+          bool STASH, bool EXT>
 __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
                                           const S* __restrict__ src, S* __restrict__ dst,
                                           const StepGeom& g, const Phys& ph, const StepAux& aux,
@@ -208,6 +212,9 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
     constexpr int EX = Lds::EX, EY = Lds::EY, NE = Lds::NE;
     constexpr int FX = Lds::FX, NF = Lds::NF;
     constexpr bool kStash = Lds::kStash;
+    // walls and body force exist only in the EXT instantiation (the periodic one has none of
+    // their code)
+    const bool has_walls = EXT && D == 3 && ph.walls != 0;
     constexpr bool kFiveRing = D == 3;   // no barrier closes an iteration
     constexpr int RING = Lds::RING, PR = Lds::PR, JR = Lds::JR, UH = Lds::UH, UZ = Lds::UZ;
     // moment slots beyond the first NTH go to threads without collision work when they fit
@@ -310,6 +317,10 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
     // the density populations, bit 1 the energy populations)
     auto load_slot = [&](int zm, int r, S (&pn)[Q], S (&pe)[Q], auto sets) {
         constexpr int SETS = decltype(sets)::value;
+        // next to a wall, a direction pulled from beyond it takes the opposite population
+        // leaving the node itself (bounce-back)
+        const bool bb_lo = has_walls && zm == 0;
+        const bool bb_hi = has_walls && zm == g.nz - 1;
         int zoff[3];
         if constexpr (D == 3) {
             zoff[0] = wrap_index(zm - 1, g.nz) * nxy;
@@ -324,12 +335,22 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b) row[a][b] = zoff[a] + m_y[r][b];
+        auto pulls = [&](auto walled) {
 #pragma unroll
-        for (int k = 0; k < Q; ++k) {
-            const int off = row[1 - L::cz[k]][1 - L::cy[k]] + m_x[r][1 - L::cx[k]];
-            if constexpr (SETS & 1) pn[k] = io.load(k, off);
-            if constexpr (SETS & 2) pe[k] = io.load(Q + k, off);
-        }
+            for (int k = 0; k < Q; ++k) {
+                int pk = k, off = row[1 - L::cz[k]][1 - L::cy[k]] + m_x[r][1 - L::cx[k]];
+                if (decltype(walled)::value && L::cz[k] != 0) {
+                    if ((L::cz[k] == 1 && bb_lo) || (L::cz[k] == -1 && bb_hi)) {
+                        pk = opposite<Q>(k);
+                        off = row[1][1] + m_x[r][1];
+                    }
+                }
+                if constexpr (SETS & 1) pn[k] = io.load(pk, off);
+                if constexpr (SETS & 2) pe[k] = io.load(Q + pk, off);
+            }
+        };
+        if (bb_lo || bb_hi) pulls(std::true_type{});
+        else pulls(std::false_type{});
     };
 
     // moments, EOS and Phi of moment slot r (plane in ring slots sm, sp, sj)
@@ -361,6 +382,20 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
             o_E[0] = dE; o_p[0] = R(p);
         }
     };
+    // the register ring advances over a plane beyond a wall too (no moments there)
+    auto shift_own = [&]() {
+#pragma unroll
+        for (int q = ZH; q > 0; --q) {
+            o_rho[q] = o_rho[q - 1]; o_jx[q] = o_jx[q - 1]; o_jy[q] = o_jy[q - 1];
+            o_jz[q] = o_jz[q - 1]; o_E[q] = o_E[q - 1]; o_p[q] = o_p[q - 1];
+        }
+        o_rho[0] = 1.0; o_jx[0] = o_jy[0] = o_jz[0] = R(0);
+        o_E[0] = 1.0; o_p[0] = R(0);
+    };
+    // planes beyond a wall: no pulls, moments or force; the stages next to the wall use the
+    // mirror values instead
+    auto beyond_wall = [&](int z) { return has_walls && (z < 0 || z >= g.nz); };
+    const bool has_g = EXT && (ph.g[0] != 0.0 || ph.g[1] != 0.0 || ph.g[2] != 0.0);
 
     // the own node's pulls for the collision at plane zc (moving directions; the rest ones
     // follow from the balances); with the stash the energy populations come from LDS
@@ -375,6 +410,8 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
             }
             if constexpr (!WN) return;
         }
+        const bool bb_lo = has_walls && zc == 0;
+        const bool bb_hi = has_walls && zc == g.nz - 1;
         const int zoc = wrap_index(zc, g.nz) * nxy;
         int zpull[3] = {zoc, zoc, zoc};
         if constexpr (D == 3) {
@@ -386,12 +423,22 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b) row[a][b] = zpull[a] + ys[b];
+        auto pulls = [&](auto walled) {
 #pragma unroll
-        for (int k = 1; k < Q; ++k) {
-            const int off = row[1 - L::cz[k]][1 - L::cy[k]] + xs[1 - L::cx[k]];
-            if constexpr (!kStash) pk_e[k] = R(io.load(Q + k, off));
-            pk_n[k] = WN ? R(io.load(k, off)) : R(0);
-        }
+            for (int k = 1; k < Q; ++k) {
+                int pk = k, off = row[1 - L::cz[k]][1 - L::cy[k]] + xs[1 - L::cx[k]];
+                if (decltype(walled)::value && L::cz[k] != 0) {
+                    if ((L::cz[k] == 1 && bb_lo) || (L::cz[k] == -1 && bb_hi)) {
+                        pk = opposite<Q>(k);
+                        off = row[1][1] + xs[1];
+                    }
+                }
+                if constexpr (!kStash) pk_e[k] = R(io.load(Q + pk, off));
+                pk_n[k] = WN ? R(io.load(pk, off)) : R(0);
+            }
+        };
+        if (bb_lo || bb_hi) pulls(std::true_type{});
+        else pulls(std::false_type{});
     };
     using WithN = std::integral_constant<bool, NMODE == kTauAny>;
 
@@ -409,12 +456,32 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
         const R ux = o_jx[ZH] * inv_rho, uy = o_jy[ZH] * inv_rho, uz = o_jz[ZH] * inv_rho;
         const R* Fo = (ZH > 0) ? fprev : fcur;
 
+        // z neighbours of the node; beyond a wall: rho mirrored, u*_z mirrored with the
+        // opposite sign, T mirrored or 2 T_wall - T (wall face held at T_wall)
+        R uzm = R(0), uzp = R(0), rzm = R(0), rzp = R(0), tzm = R(0), tzp = R(0);
+        if constexpr (D == 3) {
+            uzm = sUz[sucm][of]; uzp = sUz[sucp][of];
+            rzm = sRho[scm][of]; rzp = sRho[scp][of];
+            tzm = sT[scm][of]; tzp = sT[scp][of];
+            if (has_walls) {
+                if (zc == 0) {
+                    uzm = -sUz[uzring(zc)][of];
+                    rzm = sRho[sc][of];
+                    tzm = (ph.wall_heat & kWallTBottom) ? R(2.0 * ph.T_bottom) - T : T;
+                }
+                if (zc == g.nz - 1) {
+                    uzp = -sUz[uzring(zc)][of];
+                    rzp = sRho[sc][of];
+                    tzp = (ph.wall_heat & kWallTTop) ? R(2.0 * ph.T_top) - T : T;
+                }
+            }
+        }
         // div u* by central differences on each axis (section 6.2)
         R div = R(0.5) * (sUh[0][suc][of + 1] - sUh[0][suc][of - 1]) +
                 R(0.5) * (sUh[1][suc][of + FX] - sUh[1][suc][of - FX]);
-        if constexpr (D == 3) div += R(0.5) * (sUz[sucp][of] - sUz[sucm][of]);
-        const R dE = energy_source<D, R, FX>(p, div, rho, T, sRho[scm], sRho[sc], sRho[scp], sT[scm],
-                                             sT[sc], sT[scp], of, cond_half, flags, ph, aux);
+        if constexpr (D == 3) div += R(0.5) * (uzp - uzm);
+        const R dE = energy_source<D, R, FX>(p, div, rho, T, rzm, sRho[sc], rzp, tzm, sT[sc], tzp,
+                                             of, cond_half, flags, ph, aux);
 
         NodeCollision<Q, S, R, WN> c;
         c.setup(rho, E, ux, uy, uz, Fo[0], Fo[1], Fo[2], inv_rho, dE, keepN, keepG, omega_E,
@@ -450,7 +517,7 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
     using Ahead = std::integral_constant<int, kStash ? 1 : 3>;
     using Late = std::integral_constant<int, kStash ? 2 : 0>;
     if constexpr (PIPE) {
-        if (m_e[0] >= 0) load_slot(zstart, 0, pn0, pe0, Ahead{});
+        if (m_e[0] >= 0 && !beyond_wall(zstart)) load_slot(zstart, 0, pn0, pe0, Ahead{});
     }
     for (int it = 0; it < niter; ++it) {
         const int zm = zstart + dir * it;   // moment stage; force at zm - dir, collision at zm - 2 dir
@@ -461,40 +528,59 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
         const int sj = jring(zm);
 
         // ---------------- M: moments, EOS, Phi on the tile + 2-halo of plane zm
+        const bool ghost_m = beyond_wall(zm);
         if (m_e[0] >= 0) {
-            if constexpr (!PIPE) load_slot(zm, 0, pn0, pe0, Both{});
-            if constexpr (PIPE && Late::value != 0) load_slot(zm, 0, pn0, pe0, Late{});
-            moments(0, pn0, pe0, sm, sp, sj);
-            if constexpr (kStash) {
+            if (!ghost_m) {
+                if constexpr (!PIPE) load_slot(zm, 0, pn0, pe0, Both{});
+                if constexpr (PIPE && Late::value != 0) load_slot(zm, 0, pn0, pe0, Late{});
+                moments(0, pn0, pe0, sm, sp, sj);
+                if constexpr (kStash) {
 #pragma unroll
-                for (int k = 1; k < Q; ++k) held[k - 1] = pe0[k];
+                    for (int k = 1; k < Q; ++k) held[k - 1] = pe0[k];
+                }
+            } else {
+                shift_own();
             }
             if constexpr (PIPE) {
-                if (it + 1 < niter) load_slot(zm + dir, 0, pn0, pe0, Ahead{});
+                if (it + 1 < niter && !beyond_wall(zm + dir)) load_slot(zm + dir, 0, pn0, pe0, Ahead{});
             }
         }
+        if (!ghost_m) {
 #pragma unroll
-        for (int r = 1; r < ME; ++r) {
-            if (m_e[r] < 0) continue;
-            S pn[Q], pe[Q];
-            load_slot(zm, r, pn, pe, Both{});
-            moments(r, pn, pe, sm, sp, sj);
+            for (int r = 1; r < ME; ++r) {
+                if (m_e[r] < 0) continue;
+                S pn[Q], pe[Q];
+                load_slot(zm, r, pn, pe, Both{});
+                moments(r, pn, pe, sm, sp, sj);
+            }
         }
         __syncthreads();
 
         // ---------------- F: force and u* on the tile + 1-halo of plane zf = zm - dir ZH/2
-        if (it >= ZH) {
+        if (it >= ZH && beyond_wall(zm - dir * (ZH / 2))) {
+            fprev[0] = fcur[0]; fprev[1] = fcur[1]; fprev[2] = fcur[2];
+            fcur[0] = fcur[1] = fcur[2] = R(0);
+        } else if (it >= ZH) {
             const int zf = zm - dir * (ZH / 2);
             const int sf = ring(zf), spf = pring(zf), spfm = pring(zf - 1), spfp = pring(zf + 1);
             const int sjf = jring(zf), suhf = uhring(zf), suzf = uzring(zf);
+            // Phi beyond a wall is the mirror image: the plane itself
+            const double* pm = (has_walls && zf == 0) ? sPhi[spf] : sPhi[spfm];
+            const double* pp = (has_walls && zf == g.nz - 1) ? sPhi[spf] : sPhi[spfp];
 #pragma unroll
             for (int r = 0; r < MF; ++r) {
                 if (f_f[r] < 0) continue;
                 const int e = f_e[r];
-                double fx, fy, fz;
-                force_at<Q, EX>(sPhi[spfm], sPhi[spf], sPhi[spfp], e, ph.A, ph.inv_alpha, fx, fy, fz);
-                const R Fx = R(fx), Fy = R(fy), Fz = R(fz);
                 const int f = f_f[r];
+                double fx, fy, fz;
+                force_at<Q, EX>(pm, sPhi[spf], pp, e, ph.A, ph.inv_alpha, fx, fy, fz);
+                if (has_g) {   // body force rho g (eq:edm takes any force)
+                    const double rf = double(sRho[sf][f]);
+                    fx += rf * ph.g[0];
+                    fy += rf * ph.g[1];
+                    fz += rf * ph.g[2];
+                }
+                const R Fx = R(fx), Fy = R(fy), Fz = R(fz);
                 const R inv_rho = R(1) / sRho[sf][f];
                 sUh[0][suhf][f] = (sJ[0][sjf][f] + R(0.5) * Fx) * inv_rho;
                 sUh[1][suhf][f] = (sJ[1][sjf][f] + R(0.5) * Fy) * inv_rho;
@@ -526,13 +612,13 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
 }
 
 template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool BUF, int NMODE,
-          bool STASH>
+          bool STASH, bool EXT>
 __global__ void __launch_bounds__(NTH)
 k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const Phys ph,
        const StepAux aux)
 {
     __shared__ TileLds<Q, S, R, TX, TY, STASH> lds;
-    step_tile<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, STASH>(
+    step_tile<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, STASH, EXT>(
         lds, src, dst, g, ph, aux, xcd_logical_block(blockIdx.x, gridDim.x));
 }
 

@@ -37,8 +37,14 @@ class lbm_params(ctypes.Structure):
         ("rho_c", ctypes.c_double), ("T_c", ctypes.c_double), ("p_c", ctypes.c_double),
         ("c_v", ctypes.c_double), ("chi", ctypes.c_double), ("rhoQ", ctypes.c_double),
         ("T0_baro", ctypes.c_double), ("flags", ctypes.c_uint),
+        ("walls", ctypes.c_int), ("wall_heat", ctypes.c_uint),
+        ("T_bottom", ctypes.c_double), ("T_top", ctypes.c_double),
+        ("gravity", ctypes.c_double * 3),
     ]
 
+
+LBM_WALL_T_BOTTOM = 1
+LBM_WALL_T_TOP = 2
 
 _D = ctypes.POINTER(ctypes.c_double)
 _P = ctypes.c_void_p
@@ -119,6 +125,14 @@ def make_params(Q, shape, physics, storage_bytes=4):
     for k in ("tau", "tau_E", "A", "rho_c", "T_c", "p_c", "c_v", "chi", "rhoQ", "T0_baro"):
         setattr(p, k, float(physics[k]))
     p.flags = int(physics["flags"])
+    # walls and body force are optional keys (default: periodic box, no body force)
+    p.walls = int(physics.get("walls", 0))
+    p.wall_heat = int(physics.get("wall_heat", 0))
+    p.T_bottom = float(physics.get("T_bottom", 0.0))
+    p.T_top = float(physics.get("T_top", 0.0))
+    gv = physics.get("gravity", (0.0, 0.0, 0.0))
+    for a in range(3):
+        p.gravity[a] = float(gv[a])
     return p
 
 

@@ -122,3 +122,32 @@ def test_init_rejects_a_population_plane_over_4gb():
     assert st == lbm.LBM_EINVAL
     assert "4 GB" in lbm.lbm_last_error()
     assert not h.value
+
+
+@pytest.mark.parametrize("change, message", [
+    (dict(walls=2), "walls must be 0"),
+    (dict(walls=1, wall_heat=1, T_bottom=0.8, chi=0.15), "1/(2d + 1)"),
+    (dict(walls=1, wall_heat=2, T_top=-1.0), "held wall temperature"),
+    (dict(gravity=(0.0, float("nan"), 0.0)), "gravity must be finite"),
+])
+def test_init_rejects_bad_walls_and_body_force(change, message):
+    """Wall and body-force parameters are validated before any field is read or any device is
+    touched: walls other than 0/1, chi too large next to a held wall (its face is half a cell
+    away), a non-positive held wall temperature, a non-finite gravity."""
+    phys, rho, u, T = _case()
+    phys = dict(phys, **change)
+    p = lbm.make_params(19, (8, 6, 5), phys, storage_bytes=4)
+    h = ctypes.c_void_p()
+    st = lbm.lib().lbm_init(ctypes.byref(p), None, None, None, None, ctypes.byref(h))
+    assert st == lbm.LBM_EINVAL
+    assert message in lbm.lbm_last_error()
+    assert not h.value
+
+
+def test_init_rejects_walls_on_d2q9():
+    phys, rho, u, T = _case()
+    p = lbm.make_params(9, (1, 6, 5), dict(phys, walls=1), storage_bytes=4)
+    h = ctypes.c_void_p()
+    st = lbm.lib().lbm_init(ctypes.byref(p), None, None, None, None, ctypes.byref(h))
+    assert st == lbm.LBM_EINVAL
+    assert "walls need D3Q19" in lbm.lbm_last_error()

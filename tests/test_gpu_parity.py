@@ -68,8 +68,9 @@ def test_full_size_droplet_128_in_bench_launch():
 
 def test_full_size_spinodal_256_in_bench_launch():
     """The 256^3 spinodal workload (T~ 0.75, rho = 1 x (1 + 0.02 N(0, 1)), u = 0), FP32, in the
-    launch configuration the benchmark times (z chunk 32, 1024 workgroups), every field against
-    the oracle after 2 steps (the oracle holds 10 GB of FP64 populations for this)."""
+    launch configuration the benchmark times (the default launch with the automatic z chunk),
+    every field against the oracle after 2 steps (the oracle holds 10 GB of FP64 populations
+    for this)."""
     case = I.spinodal_3d(n=256, Tr=0.75, rho_mean=1.0, sigma=0.02)
     errs, *_ = compare(case, 2, 4)
     describe("spinodal 256^3 4B, 2 steps", errs)

@@ -1,0 +1,103 @@
+"""GPU parity of the walls and the body force (the pool-boiling setting) against the FP64
+oracle, through the C ABI.
+
+Walls normal to z halfway between planes (bounce-back of N and g; mirror ghosts for Phi, rho,
+u*_z and T), a bottom wall held above the saturation temperature of the liquid layer, a cold
+top wall and gravity along -z.  Tolerances as for the periodic cases: 1e-5 relative max-norm
+for FP32 storage, 1e-11 for FP64 storage, after 100 steps.  Every launch variant and z-chunk
+length must give bitwise identical fields with walls too (the chunks next to a wall march both
+upward and downward).  At the benchmark's 512^3 size, in its launch, mass conservation (exact
+up to FP32 rounding of the stored populations) and finiteness are checked.
+"""
+import numpy as np
+import pytest
+
+from paper_1705_10045_amd import inputs as I
+from paper_1705_10045_amd import lbm
+
+from parity import compare, describe
+
+pytestmark = pytest.mark.gpu
+
+TOL = {4: 1e-5, 8: 1e-11}
+
+
+def pool(shape=(30, 20, 24), gravity=1e-4, **phys):
+    return I.pool_boiling_3d(shape=shape, gravity=gravity, params=I.physics(**phys))
+
+
+@pytest.mark.parametrize("storage", [4, 8])
+def test_pool_boiling_100_steps(storage):
+    errs, g, o, gt, ot = compare(pool(), 100, storage)
+    describe("pool boiling %dB" % storage, errs)
+    assert max(errs.values()) < TOL[storage]
+    assert abs(gt[0] - ot[0]) / ot[0] < (1e-9 if storage == 4 else 1e-13)
+
+
+@pytest.mark.parametrize("storage", [4, 8])
+def test_pool_boiling_tau_not_one(storage):
+    errs, *_ = compare(pool(tau=0.8), 100, storage)
+    describe("pool boiling tau 0.8 %dB" % storage, errs)
+    assert max(errs.values()) < TOL[storage]
+
+
+def test_adiabatic_walls_odd_box():
+    case = pool(shape=(27, 17, 21))
+    case["params"]["wall_heat"] = 0
+    errs, *_ = compare(case, 100, 4)
+    describe("adiabatic walls 4B", errs)
+    assert max(errs.values()) < TOL[4]
+
+
+def test_pool_boiling_128_in_bench_launch():
+    """128^3 pool boiling (gravity 1e-5, as the benchmark's workload) in the default launch,
+    every field against the oracle after 10 steps."""
+    case = I.pool_boiling_3d(n=128)
+    errs, *_ = compare(case, 10, 4)
+    describe("pool boiling 128^3 4B, 10 steps", errs)
+    assert max(errs.values()) < TOL[4]
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.8])
+@pytest.mark.parametrize("storage", [4, 8])
+def test_launch_variants_are_bitwise_identical_with_walls(tau, storage):
+    case = pool(shape=(29, 18, 23), tau=tau)
+    ref = None
+    with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"],
+                 storage_bytes=storage) as s:
+        ck = s.checkpoint()
+        v = 0
+        while True:
+            for chunk in (0, 3, 7):
+                try:
+                    s.set_launch(v, chunk)
+                except lbm.LbmError:
+                    assert v > 0 and chunk == 0
+                    break
+                s.restore(ck)
+                s.step(12)
+                m = s.moments()
+                if ref is None:
+                    ref = m
+                for k in m:
+                    assert np.array_equal(m[k], ref[k]), (v, chunk, k)
+            else:
+                v += 1
+                continue
+            break
+    assert v >= 2
+
+
+def test_pool_boiling_512_in_bench_launch_conserves_mass():
+    """The benchmark's 512^3 pool-boiling workload (40.8 GB state, global addressing) in its
+    launch: after 3 steps the FP64 mass total equals the initial one up to FP32 rounding of
+    the stored populations, and every field is finite."""
+    case = I.pool_boiling_3d(n=512)
+    with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"]) as s:
+        m0 = s.reduce()[0]
+        s.step(3)
+        m1, e1 = s.reduce()[0], s.reduce()[4]
+    del case
+    print("512^3 pool boiling: mass %.17g -> %.17g (rel %.2e)" % (m0, m1, (m1 - m0) / m0))
+    assert abs(m1 - m0) / m0 < 1e-8
+    assert np.isfinite(e1)
