@@ -224,9 +224,10 @@ hipError_t launch_one(const void* src, void* dst, const StepGeom& g, const Phys&
 // for the LDS stash, it is used where it measured faster on MI355X and fits the registers:
 //   - FP32 with buffer addressing, any tau; the density prefetch stays on for tau = 1 only
 //     (re-reading N_k in the collision leaves no registers for it);
-//   - FP64 (global addressing) for tau = 1 (with a collision that re-reads N_k it spills);
-//   - not with FP32 global addressing (states of 4 GB and more), where the prefetch alone is
-//     faster.
+//   - global addressing (FP32 states of 4 GB and more, FP64), without the prefetch: at 512^3
+//     the step is bound by HBM traffic, and the stash saves the collision's second pull of the
+//     energy populations (12.6 ms against 14.4 ms for the prefetch alone);
+//   - not for FP64 with a collision that re-reads N_k (it would spill).
 template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool STASH = false,
           bool GLOBAL = false>
 hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Phys& ph,
@@ -239,9 +240,9 @@ hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Ph
                         : launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, true, kTauAny>(src, dst, g, ph, aux, st);
         }
     }
-    constexpr bool kStashGlobal = STASH && sizeof(S) == 8;
-    return tau1 ? launch_one<Q, S, R, TX, TY, NTH, PIPE, kStashGlobal, false, kTauOne>(src, dst, g, ph, aux, st)
-                : launch_one<Q, S, R, TX, TY, NTH, PIPE, false, false, kTauAny>(src, dst, g, ph, aux, st);
+    constexpr bool kStashAnyTau = STASH && sizeof(S) == 4;
+    return tau1 ? launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, false, kTauOne>(src, dst, g, ph, aux, st)
+                : launch_one<Q, S, R, TX, TY, NTH, PIPE && !kStashAnyTau, kStashAnyTau, false, kTauAny>(src, dst, g, ph, aux, st);
 }
 
 }  // namespace
