@@ -7,7 +7,8 @@ top wall and gravity along -z.  Tolerances as for the periodic cases: 1e-5 relat
 for FP32 storage, 1e-11 for FP64 storage, after 100 steps.  Every launch variant and z-chunk
 length must give bitwise identical fields with walls too (the chunks next to a wall march both
 upward and downward).  At the benchmark's 512^3 size, in its launch, mass conservation (exact
-up to FP32 rounding of the stored populations) and finiteness are checked.
+up to FP32 rounding of the stored populations) and finiteness are checked.  The body force is
+also checked without walls, on a periodic D3Q19 droplet and a D2Q9 slab.
 """
 import numpy as np
 import pytest
@@ -101,3 +102,23 @@ def test_pool_boiling_512_in_bench_launch_conserves_mass():
     print("512^3 pool boiling: mass %.17g -> %.17g (rel %.2e)" % (m0, m1, (m1 - m0) / m0))
     assert abs(m1 - m0) / m0 < 1e-8
     assert np.isfinite(e1)
+
+
+@pytest.mark.parametrize("storage", [4, 8])
+def test_body_force_on_a_periodic_droplet(storage):
+    """Gravity without walls (periodic D3Q19 droplet, tilted g): the body force alone."""
+    case = I.droplet_3d(shape=(28, 24, 20), radius=6.0, velocity=(0.02, 0.0, 0.0))
+    case["params"] = dict(case["params"], gravity=(2e-5, -1e-4, 5e-5))
+    errs, g, o, gt, ot = compare(case, 100, storage)
+    describe("periodic droplet with gravity %dB" % storage, errs)
+    assert max(errs.values()) < TOL[storage]
+    for a in range(3):   # momentum totals agree too (no walls: the stored populations' momentum)
+        assert abs(gt[1 + a] - ot[1 + a]) < 1e-6 * ot[0]
+
+
+def test_body_force_on_a_d2q9_slab():
+    case = I.slab_2d(n=64, width=20)
+    case["params"] = dict(case["params"], gravity=(0.0, -1e-4, 0.0))
+    errs, *_ = compare(case, 100, 8)
+    describe("D2Q9 slab with gravity 8B", errs)
+    assert max(errs.values()) < TOL[8]
