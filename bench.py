@@ -187,9 +187,14 @@ def serving_bench(count=48, steps_range=(100, 1000), budget_gib=4.0, max_slots=6
     # the initial fields arrive with each request (the client builds them): not timed
     payload = {r["id"]: I.request_fields(r) for r in reqs}
 
+    def progress(done):   # a line every 64 requests, so long streams show progress
+        if done % 64 == 0:
+            print("serving: %d of %d requests done" % (done, count), file=sys.stderr, flush=True)
+
     def run(arrivals):
         with lbm.Pool(budget, max_slots=max_slots, steps_per_run=steps_per_run) as pool:
-            return serve.serve(reqs, arrivals, serve.PoolExecutor(pool, payload=payload))
+            return serve.serve(reqs, arrivals, serve.PoolExecutor(pool, payload=payload),
+                               progress=progress)
 
     print("serving: burst of %d requests" % count, file=sys.stderr, flush=True)
     burst = run(np.zeros(count))
@@ -197,12 +202,13 @@ def serving_bench(count=48, steps_range=(100, 1000), budget_gib=4.0, max_slots=6
     print("serving: Poisson stream at %.2f requests/s" % rate, file=sys.stderr, flush=True)
     stream = run(serve.poisson_arrivals(count, rate))
     print("serving: one at a time", file=sys.stderr, flush=True)
-    single = serve.one_at_a_time(reqs, payload=payload)
+    single = serve.one_at_a_time(reqs, payload=payload, progress=progress)
 
     def brief(r):
         return {"p50_s": round(r["p50_s"], 4), "p99_s": round(r["p99_s"], 4),
                 "aggregate_mlups": round(r["aggregate_mlups"], 1), "wall_s": round(r["wall_s"], 3),
                 "completed": r["completed"], "failed": r["failed"],
+                "failed_ids": [reqs[i]["id"] for i, st in enumerate(r["status"]) if st not in (0, None)],
                 "peak_in_flight": r["peak_in_flight"], "replays": r["replays"]}
     return {"requests": count, "edges": sorted(set(r["edge"] for r in reqs)),
             "steps_range": list(steps_range), "node_updates": int(work.sum()),
@@ -212,7 +218,8 @@ def serving_bench(count=48, steps_range=(100, 1000), budget_gib=4.0, max_slots=6
             "poisson": dict(brief(stream), offered_load=load,
                             rate_per_s=round(rate, 3)),
             "one_at_a_time_mlups": round(single["aggregate_mlups"], 1),
-            "one_at_a_time_wall_s": round(single["wall_s"], 3)}
+            "one_at_a_time_wall_s": round(single["wall_s"], 3),
+            "one_at_a_time_failed_ids": single["failed_ids"]}
 
 
 def sweep(sim, stream, n, storage, chunks=(0, 8, 16, 32), steps=40, reps=3):
@@ -283,6 +290,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving measurement in the default line")
     ap.add_argument("--serving-requests", type=int, default=48)
+    ap.add_argument("--serving-full", action="store_true",
+                    help="with --serving: the full request stream (512 requests, 500..5000 steps, "
+                         "64 GiB pool) instead of the short default")
     ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--chunk", type=int, default=0)
     args = ap.parse_args()
@@ -305,8 +315,12 @@ def main():
         lib_build.build()
 
     if args.serving:
+        if args.serving_full:   # the serving configuration as listed: 512 requests, 500..5000 steps
+            rep = serving_bench(count=512, steps_range=(500, 5000), budget_gib=64.0)
+        else:
+            rep = serving_bench(count=args.serving_requests)
         print(json.dumps({"metric": "serving time-to-result (p50/p99) and aggregate MLUPS",
-                          "serving": serving_bench(count=args.serving_requests)}), flush=True)
+                          "serving": rep}), flush=True)
         return
 
     case, storage, config = workload(args.workload)

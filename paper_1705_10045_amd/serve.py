@@ -81,10 +81,11 @@ class PoolExecutor:
 
 
 def serve(requests, arrivals, executor, clock=time.perf_counter, sleep=time.sleep,
-          keep_results=False):
+          keep_results=False, progress=None):
     """Run the continuous-batching loop.  Returns a report dict with per-request latencies,
     p50/p99 time-to-result, aggregate node updates per second and the peak number of requests
-    in flight.  `requests[i]` arrives at `arrivals[i]` seconds after the start."""
+    in flight.  `requests[i]` arrives at `arrivals[i]` seconds after the start.  `progress`,
+    if given, is called with the number of completed requests after each completion."""
     order = sorted(range(len(requests)), key=lambda i: (arrivals[i], i))
     pending = collections.deque(order)
     waiting = []                         # arrived, not yet admitted (arrival order)
@@ -132,6 +133,8 @@ def serve(requests, arrivals, executor, clock=time.perf_counter, sleep=time.slee
             if st == 0:
                 r = requests[i]
                 node_updates += r["edge"] ** 3 * r["steps"]
+            if progress:
+                progress(len(latency))
     wall = clock() - t0
     lat = [latency[i] for i in range(len(requests)) if status.get(i) == 0]
     report = {
@@ -150,19 +153,29 @@ def serve(requests, arrivals, executor, clock=time.perf_counter, sleep=time.slee
     return report
 
 
-def one_at_a_time(requests, physics=None, clock=time.perf_counter, payload=None):
+def one_at_a_time(requests, physics=None, clock=time.perf_counter, payload=None, progress=None):
     """The same requests solved one after another with a single simulation each (lbm_init,
     lbm_step, lbm_moments, lbm_free): aggregate node updates per second.  `payload` as for
-    PoolExecutor."""
+    PoolExecutor; `progress` as for serve.  A request that leaves the EOS domain counts as
+    failed (its time counts, its node updates do not), as in the pool."""
     from . import lbm
     physics = physics or inputs.physics()
     t0 = clock()
     total = 0
-    for r in requests:
+    failed = []
+    for n_done, r in enumerate(requests, 1):
         f = payload[r["id"]] if payload else inputs.request_fields(r, physics)
         with lbm.Sim(19, f["params"], f["rho0"], f["u0"], f["T0"], storage_bytes=4) as s:
-            s.step(r["steps"])
-            s.moments()
-        total += r["edge"] ** 3 * r["steps"]
+            try:
+                s.step(r["steps"])
+                s.moments()
+                total += r["edge"] ** 3 * r["steps"]
+            except lbm.LbmError as e:
+                if e.status != lbm.LBM_EUNSTABLE:
+                    raise
+                failed.append(r["id"])
+        if progress:
+            progress(n_done)
     wall = clock() - t0
-    return {"wall_s": wall, "node_updates": total, "aggregate_mlups": total / wall / 1e6}
+    return {"wall_s": wall, "node_updates": total, "aggregate_mlups": total / wall / 1e6,
+            "failed_ids": failed}
