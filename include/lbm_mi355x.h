@@ -114,8 +114,10 @@ lbm_status lbm_step_async(lbm_sim* sim, int nsteps);
 lbm_status lbm_check(lbm_sim* sim);
 
 /* Fields of the current state: rho = sum N_k and E = sum g_k (eq:hydro, section 4),
- * u* = (sum c_k N_k + F/2)/rho (eq:ustar), T = E/(rho c_v).  Each argument is a caller-owned
- * host FP64 array of n values (u_star: 3n), or NULL to skip it.  Synchronises. */
+ * u* = (sum c_k N_k + F/2)/rho (eq:ustar) with F the force of section 3 plus the body force
+ * rho g, T = E/(rho c_v).  With walls, the populations pulled from beyond a wall are the
+ * bounced-back ones, as in the step.  Each argument is a caller-owned host FP64 array of n
+ * values (u_star: 3n), or NULL to skip it.  Synchronises. */
 lbm_status lbm_moments(lbm_sim* sim, double* rho, double* u_star, double* E, double* T);
 
 /* Same as lbm_moments but into caller-owned device FP64 arrays on the simulation's device;
