@@ -18,6 +18,9 @@
  *   7. BGK collision + dg(1) + pseudoforce dg(2) of g_k               eq:gk, section 4
  *   8. streaming to x + c_k, periodic                                 eq:lbe, eq:gk
  *
+ * Lattices: D1Q3 (ny = nz = 1), D2Q9 (nz = 1) and D3Q19, with the force coefficients
+ * G_k of section 3 (neighbours along the axes and, for D2Q9/D3Q19, the diagonals).
+ *
  * Walls and body force (not in the paper; readings listed in the design notes): optional
  * no-slip walls normal to z halfway between planes (bounce-back of N and g in step 8; mirror
  * ghosts beyond them in steps 3 and 5) and F += rho g in step 3.
@@ -72,6 +75,18 @@ static int make_lattice(int Q, lattice* L)
 {
     memset(L, 0, sizeof(*L));
     L->Q = Q;
+    if (Q == 3) {            /* D1Q3: the paper's one-dimensional lattice */
+        static const int c3[3][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}};
+        L->D = 1;
+        for (int k = 0; k < 3; ++k) {
+            for (int a = 0; a < 3; ++a) L->c[k][a] = c3[k][a];
+            L->w[k] = k == 0 ? 2.0 / 3.0 : 1.0 / 6.0;
+            L->G[k] = k == 0 ? 0.0 : 1.0;
+        }
+        L->alpha = 1.0;
+        find_opposites(L);
+        return 1;
+    }
     if (Q == 9) {
         static const int c9[9][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
                                      {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
@@ -412,9 +427,10 @@ static double* alloc0(long n)
 
 static int valid_params(const orc_params* p)
 {
-    if (!(p->Q == 9 || p->Q == 19)) return 0;
+    if (!(p->Q == 3 || p->Q == 9 || p->Q == 19)) return 0;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return 0;
     if (p->Q == 9 && p->nz != 1) return 0;
+    if (p->Q == 3 && (p->ny != 1 || p->nz != 1)) return 0;
     if (!(p->tau > 0.5 && p->tau_E > 0.5)) return 0;
     if (!(p->rho_c > 0 && p->T_c > 0 && p->p_c > 0 && p->c_v > 0)) return 0;
     if (!(p->chi >= 0)) return 0;

@@ -35,7 +35,7 @@ extern "C" {
 #define ORC_EUNSTABLE -3
 
 typedef struct {
-    int Q;                 /* 9 (D2Q9, nz must be 1) or 19 (D3Q19)            */
+    int Q;                 /* 3 (D1Q3, ny = nz = 1), 9 (D2Q9, nz = 1), 19 (D3Q19) */
     int nx, ny, nz;        /* periodic box                                    */
     double tau, tau_E;     /* BGK relaxation times of N_k and g_k             */
     double A;              /* force mixing parameter (section 3)              */

@@ -1,5 +1,6 @@
 """Pins of the oracle's lattice tables and equilibrium (section 2, eq:feq; section 3 force
-coefficients) against identities that any correct D2Q9 / D3Q19 velocity set must satisfy."""
+coefficients) against identities that any correct D1Q3 / D2Q9 / D3Q19 velocity set must
+satisfy."""
 import itertools
 
 import numpy as np
@@ -8,15 +9,17 @@ import pytest
 THETA = 1.0 / 3.0
 
 
-@pytest.mark.parametrize("Q,D,alpha", [(9, 2, 1.5), (19, 3, 3.0)])
+@pytest.mark.parametrize("Q,D,alpha", [(3, 1, 1.0), (9, 2, 1.5), (19, 3, 3.0)])
 def test_velocity_set_shape(orc, Q, D, alpha):
     c, w, G, a, d = orc.lattice(Q)
     assert d == D and a == alpha
     # distinct velocities, one rest particle, |c|^2 in {1, 2} otherwise
     assert len({tuple(v) for v in c}) == Q
     sq = (c * c).sum(1)
-    assert sq[0] == 0 and set(sq[1:]) == {1, 2}
-    if D == 2:
+    assert sq[0] == 0 and set(sq[1:]) == ({1} if D == 1 else {1, 2})
+    if D == 1:
+        assert (c[:, 1:] == 0).all()
+    elif D == 2:
         assert (c[:, 2] == 0).all()
         assert (sq == 1).sum() == 4 and (sq == 2).sum() == 4
     else:
@@ -29,7 +32,7 @@ def test_velocity_set_shape(orc, Q, D, alpha):
         assert w[opp[0]] == w[k] and G[opp[0]] == G[k]
 
 
-@pytest.mark.parametrize("Q", [9, 19])
+@pytest.mark.parametrize("Q", [3, 9, 19])
 def test_weight_moments_isotropic_to_fourth_order(orc, Q):
     """sum w = 1, sum w c = 0, sum w c c = theta I, odd moments vanish,
     sum w c_a c_b c_c c_d = theta^2 (d_ab d_cd + d_ac d_bd + d_ad d_bc) on the D active axes."""
@@ -46,7 +49,7 @@ def test_weight_moments_isotropic_to_fourth_order(orc, Q):
     assert np.allclose(m4, iso, atol=1e-15)
 
 
-@pytest.mark.parametrize("Q", [9, 19])
+@pytest.mark.parametrize("Q", [3, 9, 19])
 def test_force_coefficients(orc, Q):
     """sum G e = 0, sum G e e e = 0 and sum G e e = 2 alpha I, so that the discrete force of
     section 3 reduces to grad(Phi^2) for smooth Phi."""
@@ -62,7 +65,7 @@ def test_force_coefficients(orc, Q):
     assert (G[sq == 2] == (0.25 if Q == 9 else 0.5)).all()
 
 
-@pytest.mark.parametrize("Q", [9, 19])
+@pytest.mark.parametrize("Q", [3, 9, 19])
 def test_collapse_to_d1q3(orc, Q):
     """Grouping directions by c_x gives the D1Q3 weights {2/3, 1/6, 1/6} of section 2 and a
     force coefficient sum equal to alpha per side (alpha = 1 for D1Q3 after dividing)."""
@@ -73,7 +76,7 @@ def test_collapse_to_d1q3(orc, Q):
     assert G[c[:, 0] == -1].sum() == pytest.approx(alpha)
 
 
-@pytest.mark.parametrize("Q", [9, 19])
+@pytest.mark.parametrize("Q", [3, 9, 19])
 def test_equilibrium_moments(orc, Q):
     """eq:feq has density rho, momentum rho u and momentum flux rho theta I + rho u u exactly
     (a consequence of the lattice identities above, evaluated on the oracle's function)."""
@@ -91,7 +94,7 @@ def test_equilibrium_moments(orc, Q):
         assert np.allclose(Pi, rho * THETA * np.eye(D) + rho * np.outer(u[:D], u[:D]), atol=1e-14)
 
 
-@pytest.mark.parametrize("Q", [9, 19])
+@pytest.mark.parametrize("Q", [3, 9, 19])
 def test_edm_increment_moments(orc, Q):
     """eq:edm: dN = Neq(rho,u+du) - Neq(rho,u) adds no mass and exactly rho du of momentum."""
     c, _, _, _, D = orc.lattice(Q)
