@@ -23,6 +23,9 @@ PSEUDOFORCE = 8
 BAROTROPIC = 16
 ALL_TERMS = WORK | CONDUCTION | LATENT | PSEUDOFORCE
 
+BGK = 0
+MRT = 1
+
 WALL_T_BOTTOM = 1
 WALL_T_TOP = 2
 
@@ -41,6 +44,9 @@ class _Params(ctypes.Structure):
         ("walls", ctypes.c_int), ("wall_heat", ctypes.c_uint),
         ("T_bottom", ctypes.c_double), ("T_top", ctypes.c_double),
         ("gravity", ctypes.c_double * 3),
+        ("collision", ctypes.c_int),
+        ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double), ("s_q", ctypes.c_double),
+        ("s_m", ctypes.c_double),
     ]
 
 
@@ -59,6 +65,7 @@ def _lib():
         lib.orc_maxwell.argtypes = [ctypes.c_double, _D, _D, _D]
         lib.orc_lattice.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D, _D, _D]
         lib.orc_equilibrium.argtypes = [ctypes.c_int, ctypes.c_double, _D, _D]
+        lib.orc_mrt_basis.argtypes = [ctypes.c_int, _D, _D, ctypes.POINTER(ctypes.c_int)]
         lib.orc_force.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double, _D, _D]
         lib.orc_divergence.argtypes = [ctypes.c_int] * 4 + [_D, _D]
         lib.orc_conduction.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double] * 2 + [_D, _D, _D]
@@ -100,6 +107,18 @@ def lattice(Q):
     if D < 0:
         raise ValueError("unsupported lattice Q=%d" % Q)
     return np.array(list(c), dtype=np.int64).reshape(Q, 3), w, G, alpha.value, D
+
+
+def mrt_basis(Q):
+    """(M[Q,Q], squared row norms[Q], group[Q]) of the MRT moment basis, rows in the oracle's
+    velocity order; groups 0 conserved, 1 shear, 2 energy, 3 energy square and fourth order,
+    4 energy flux, 5 third order."""
+    M = np.zeros(Q * Q)
+    n2 = np.zeros(Q)
+    grp = (ctypes.c_int * Q)()
+    if _lib().orc_mrt_basis(Q, _ptr(M), _ptr(n2), grp) != OK:
+        raise ValueError("no MRT basis for Q=%d" % Q)
+    return M.reshape(Q, Q), n2, np.array(list(grp))
 
 
 def vdw_reduced(rr, Tr):
@@ -184,6 +203,9 @@ _PARAM_KEYS = ("tau", "tau_E", "A", "rho_c", "T_c", "p_c", "c_v", "chi", "rhoQ",
 _WALL_DEFAULTS = {"walls": 0, "wall_heat": 0, "T_bottom": 0.0, "T_top": 0.0,
                   "gravity": (0.0, 0.0, 0.0)}
 
+# the collision form is optional too (default BGK); the MRT rates matter only with MRT
+_MRT_DEFAULTS = {"collision": BGK, "s_e": 1.0, "s_eps": 1.0, "s_q": 1.0, "s_m": 1.0}
+
 
 class Sim:
     """One simulation on the CPU in FP64 (periodic, or with walls normal to z)."""
@@ -203,6 +225,9 @@ class Sim:
         gv = params.get("gravity", _WALL_DEFAULTS["gravity"])
         for a in range(3):
             p.gravity[a] = float(gv[a])
+        p.collision = int(params.get("collision", _MRT_DEFAULTS["collision"]))
+        for k in ("s_e", "s_eps", "s_q", "s_m"):
+            setattr(p, k, float(params.get(k, _MRT_DEFAULTS[k])))
         self.Q, self.shape = Q, rho0.shape
         self._p = p
         st = ctypes.c_int()

@@ -37,6 +37,9 @@
  *     where 0.4 <= T~ < 0.999 and rho_1(T) < rho < rho_2(T) strictly, with
  *     rho_1, rho_2 the Maxwell coexistence densities at the EOS temperature.
  *
+ * Collision of N_k: BGK (eq:lbe) or, as section 2 also allows, multiple relaxation times on an
+ * orthogonal moment basis (MRT), with the EDM increment added in either case.
+ *
  * Every function is pinned by the CPU test suite against closed forms, exact
  * invariants, independent spectral/quadrature computations or values printed in
  * the paper; none is "parity unpinned".
@@ -51,6 +54,9 @@
 #define LATENT_TMIN 0.4            /* reduced-temperature window of the latent source */
 #define LATENT_TMAX 0.999
 
+/* Moment groups of the multiple-relaxation-time collision: which rate relaxes moment i. */
+enum { MG_CONSERVED = 0, MG_SHEAR = 1, MG_BULK = 2, MG_EPS = 3, MG_Q = 4, MG_M = 5 };
+
 typedef struct {
     int Q, D;
     int c[19][3];
@@ -58,7 +64,52 @@ typedef struct {
     double w[19];
     double G[19];
     double alpha;
+    /* MRT moment basis (D2Q9 and D3Q19): row i of M holds moment i's polynomial evaluated at
+     * every velocity; rows are orthogonal, M2[i] = sum_k M[i][k]^2; grp[i] is its group. */
+    double M[19][19];
+    double M2[19];
+    int grp[19];
 } lattice;
+
+/* Orthogonal moment bases of the MRT collision named in section 2 (Lallemand and Luo 2000 for
+ * D2Q9, d'Humieres et al. 2002 for D3Q19), written as polynomials of the velocity: density,
+ * energy e, energy square eps, momentum j, energy flux q, the traceless stresses (shear),
+ * and for D3Q19 the fourth-order pi and third-order m moments. */
+static void mrt_basis(lattice* L)
+{
+    for (int k = 0; k < L->Q; ++k) {
+        const double x = L->c[k][0], y = L->c[k][1], z = L->c[k][2];
+        const double c2 = x * x + y * y + z * z;
+        double r[19];
+        if (L->Q == 9) {
+            const double v[9] = {1.0, 3.0 * c2 - 4.0, 4.5 * c2 * c2 - 10.5 * c2 + 4.0,
+                                 x, (3.0 * c2 - 5.0) * x, y, (3.0 * c2 - 5.0) * y,
+                                 x * x - y * y, x * y};
+            memcpy(r, v, sizeof(v));
+        } else {
+            const double v[19] = {1.0, 19.0 * c2 - 30.0, (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0,
+                                  x, (5.0 * c2 - 9.0) * x, y, (5.0 * c2 - 9.0) * y,
+                                  z, (5.0 * c2 - 9.0) * z,
+                                  3.0 * x * x - c2, (3.0 * c2 - 5.0) * (3.0 * x * x - c2),
+                                  y * y - z * z, (3.0 * c2 - 5.0) * (y * y - z * z),
+                                  x * y, y * z, x * z,
+                                  (y * y - z * z) * x, (z * z - x * x) * y, (x * x - y * y) * z};
+            memcpy(r, v, sizeof(v));
+        }
+        for (int i = 0; i < L->Q; ++i) L->M[i][k] = r[i];
+    }
+    static const int g9[9] = {MG_CONSERVED, MG_BULK, MG_EPS, MG_CONSERVED, MG_Q, MG_CONSERVED,
+                              MG_Q, MG_SHEAR, MG_SHEAR};
+    static const int g19[19] = {MG_CONSERVED, MG_BULK, MG_EPS, MG_CONSERVED, MG_Q, MG_CONSERVED,
+                                MG_Q, MG_CONSERVED, MG_Q, MG_SHEAR, MG_EPS, MG_SHEAR, MG_EPS,
+                                MG_SHEAR, MG_SHEAR, MG_SHEAR, MG_M, MG_M, MG_M};
+    for (int i = 0; i < L->Q; ++i) {
+        L->grp[i] = L->Q == 9 ? g9[i] : g19[i];
+        double n2 = 0.0;
+        for (int k = 0; k < L->Q; ++k) n2 += L->M[i][k] * L->M[i][k];
+        L->M2[i] = n2;
+    }
+}
 
 /* opp[k]: the direction with the opposite velocity, found by search */
 static void find_opposites(lattice* L)
@@ -99,6 +150,7 @@ static int make_lattice(int Q, lattice* L)
         }
         L->alpha = 1.5;
         find_opposites(L);
+        mrt_basis(L);
         return 2;
     }
     if (Q == 19) {
@@ -117,6 +169,7 @@ static int make_lattice(int Q, lattice* L)
         }
         L->alpha = 3.0;
         find_opposites(L);
+        mrt_basis(L);
         return 3;
     }
     return ORC_EINVAL;
@@ -133,6 +186,18 @@ int orc_lattice(int Q, int* c, double* w, double* G, double* alpha)
     }
     *alpha = L.alpha;
     return L.D;
+}
+
+int orc_mrt_basis(int Q, double* M, double* norm2, int* group)
+{
+    lattice L;
+    if (!(Q == 9 || Q == 19) || make_lattice(Q, &L) < 0) return ORC_EINVAL;
+    for (int i = 0; i < Q; ++i) {
+        for (int k = 0; k < Q; ++k) M[i * Q + k] = L.M[i][k];
+        norm2[i] = L.M2[i];
+        group[i] = L.grp[i];
+    }
+    return ORC_OK;
 }
 
 /* ---------------------------------------------------------------------------
@@ -449,6 +514,13 @@ static int valid_params(const orc_params* p)
     }
     for (int a = 0; a < 3; ++a)
         if (!isfinite(p->gravity[a])) return 0;
+    if (p->collision != ORC_BGK && p->collision != ORC_MRT) return 0;
+    if (p->collision == ORC_MRT) {
+        if (!(p->Q == 9 || p->Q == 19)) return 0;
+        const double r[4] = {p->s_e, p->s_eps, p->s_q, p->s_m};
+        for (int i = 0; i < 4; ++i)
+            if (!(r[i] > 0.0 && r[i] < 2.0)) return 0;
+    }
     return 1;
 }
 
@@ -613,9 +685,28 @@ static void pass_collide(orc_sim* s)
         equilibrium(&s->L, s->rho[i], v, Neq_v);
         equilibrium(&s->L, s->E[i], u, geq_u);
         equilibrium(&s->L, s->E[i], v, geq_v);
+        if (p->collision == ORC_MRT) {
+            /* multiple relaxation times: the non-equilibrium part N - Neq(rho, u) relaxes moment
+             * by moment, m_i -> m_i (1 - s_i), with the shear rate 1/tau; the EDM increment is
+             * added as for BGK.  With every rate equal to 1/tau this is the BGK update. */
+            const double rate[6] = {0.0, 1.0 / p->tau, p->s_e, p->s_eps, p->s_q, p->s_m};
+            double fneq[19], m[19];
+            for (int k = 0; k < Q; ++k) fneq[k] = s->N[i * Q + k] - Neq_u[k];
+            for (int a = 0; a < Q; ++a) {
+                m[a] = 0.0;
+                for (int k = 0; k < Q; ++k) m[a] += s->L.M[a][k] * fneq[k];
+            }
+            for (int k = 0; k < Q; ++k) {
+                double relax = 0.0;
+                for (int a = 0; a < Q; ++a)
+                    relax += rate[s->L.grp[a]] * m[a] / s->L.M2[a] * s->L.M[a][k];
+                s->Np[i * Q + k] = Neq_v[k] + fneq[k] - relax;
+            }
+        }
         for (int k = 0; k < Q; ++k) {
             double N = s->N[i * Q + k];
-            s->Np[i * Q + k] = N + (Neq_u[k] - N) / p->tau + (Neq_v[k] - Neq_u[k]);
+            if (p->collision != ORC_MRT)
+                s->Np[i * Q + k] = N + (Neq_u[k] - N) / p->tau + (Neq_v[k] - Neq_u[k]);
             double g = s->g[i * Q + k];
             double gnew = g + (geq_u[k] - g) / p->tau_E + g * s->dE[i] / s->E[i];
             if (p->flags & ORC_PSEUDOFORCE) gnew += geq_v[k] - geq_u[k];

@@ -30,6 +30,9 @@ extern "C" {
 #define ORC_WALL_T_BOTTOM 1u /* z = -1/2 held at T_bottom                            */
 #define ORC_WALL_T_TOP    2u /* z = nz - 1/2 held at T_top                           */
 
+#define ORC_BGK 0           /* collision of N_k: one relaxation time tau (section 2)   */
+#define ORC_MRT 1           /* several relaxation times on an orthogonal moment basis */
+
 #define ORC_OK         0
 #define ORC_EINVAL    -1
 #define ORC_EUNSTABLE -3
@@ -54,10 +57,22 @@ typedef struct {
     /* Uniform body force per unit mass: F += rho g at every node (section 2, external force
      * through the exact difference method). */
     double gravity[3];
+    /* Collision of the density populations (section 2 names both forms): ORC_BGK, or ORC_MRT
+     * with the shear moments relaxed at 1/tau, the energy moment e at s_e (bulk viscosity),
+     * the energy-square and fourth-order moments at s_eps, the energy fluxes q at s_q and (D3Q19)
+     * the third-order moments m at s_m, each rate in (0, 2).  D2Q9 and D3Q19 only.  The energy
+     * populations g_k keep the single relaxation time tau_E of eq:gk. */
+    int collision;
+    double s_e, s_eps, s_q, s_m;
 } orc_params;
 
 /* Lattice tables: c[Q*3], w[Q], G[Q] (G[0] = 0), alpha.  Returns D or ORC_EINVAL. */
 int orc_lattice(int Q, int* c, double* w, double* G, double* alpha);
+
+/* MRT moment basis of D2Q9 or D3Q19: M[Q*Q] (row i = moment i at every velocity, in the
+ * oracle's velocity order), norm2[Q] = squared row norms, group[Q] = 0 conserved, 1 shear,
+ * 2 energy e, 3 energy square and fourth-order, 4 energy flux q, 5 third-order m. */
+int orc_mrt_basis(int Q, double* M, double* norm2, int* group);
 
 /* Reduced van der Waals pressure p~(rho~, T~) (section 3). */
 double orc_vdw_reduced(double rr, double Tr);
