@@ -45,6 +45,13 @@ enum {
     LBM_WALL_T_TOP = 2u      /* wall above z = nz - 1 held at T_top                          */
 };
 
+/* Collision of the density populations N_k (lbm_params.collision).  Section 2 names both the
+ * single-relaxation-time (BGK) form it uses and the multiple-relaxation-time (MRT) form. */
+enum {
+    LBM_COLLISION_BGK = 0,  /* N_k relaxes toward Neq(rho, u) at 1/tau                       */
+    LBM_COLLISION_MRT = 1   /* moments of N_k - Neq(rho, u) relax at their own rates         */
+};
+
 /* Physical terms (the ablations of sections 4-6). */
 enum {
     LBM_WORK = 1u,         /* pressure work -p div u*                                      */
@@ -57,8 +64,9 @@ enum {
 typedef struct {
     int lattice;          /* 9 = D2Q9 (nz must be 1) or 19 = D3Q19                           */
     int nx, ny, nz;       /* periodic box, each >= 1                                         */
-    int storage_bytes;    /* 4 = FP32 populations (FP32 arithmetic, FP64 EOS and latent band),
-                             8 = FP64 populations and arithmetic                             */
+    int storage_bytes;    /* 4 = FP32 populations (D3Q19: FP32 arithmetic with FP64 EOS and
+                             latent band; D2Q9: FP64 arithmetic), 8 = FP64 populations and
+                             arithmetic                                                      */
     double tau, tau_E;    /* BGK relaxation times of N_k and g_k, both > 1/2                 */
     double A;             /* force mixing parameter of section 3 (the paper uses -0.152)     */
     double rho_c, T_c, p_c; /* critical point of the reduced vdW EOS, lattice units         */
@@ -82,6 +90,17 @@ typedef struct {
     /* Uniform body force per unit mass (gravity): F += rho g at every node, applied by the
      * exact difference method like the interparticle force (eq:edm).  Zero for none. */
     double gravity[3];
+    /* Collision of N_k.  LBM_COLLISION_MRT relaxes, on an orthogonal moment basis (Lallemand
+     * and Luo 2000 for D2Q9, d'Humieres et al. 2002 for D3Q19), the traceless stresses at
+     * 1/tau (so the shear viscosity is (tau - 1/2)/3 as with BGK), the energy moment e at s_e
+     * (bulk viscosity), the energy-square and fourth-order moments at s_eps, the energy fluxes
+     * at s_q and, for D3Q19, the third-order moments at s_m; each rate in (0, 2).  Density and
+     * momentum are conserved as with BGK, and the EDM increment (eq:edm) is added unchanged.
+     * The energy populations keep the single relaxation time tau_E of eq:gk.  With every rate
+     * equal to 1/tau the update is the BGK one up to rounding.  The rates are ignored with
+     * LBM_COLLISION_BGK. */
+    int collision;
+    double s_e, s_eps, s_q, s_m;
 } lbm_params;
 
 typedef struct lbm_sim lbm_sim;
@@ -93,7 +112,8 @@ typedef struct lbm_sim lbm_sim;
  * Rejects (LBM_EINVAL) tau or tau_E <= 1/2, lattice/shape mismatch, walls other than 0 or 1,
  * walls with D2Q9 or with nz < 2, a held wall temperature that is not positive, chi >=
  * 1/(2d + 1) with conduction and a held wall (its face is half a cell away), a non-finite
- * gravity, a box whose population
+ * gravity, a collision other than LBM_COLLISION_BGK / _MRT or an MRT rate outside (0, 2), a
+ * box whose population
  * plane (nx*ny*nz values) would exceed 4 GB (beyond any state that fits in HBM), chi >= 0.5/d with
  * conduction on (d = number of axes with extent > 1; section 6.1), a non-positive or
  * non-finite field, rho0/rho_c >= 3, Phi^2 = rho theta - p <= 0 at any node (section 3), and
@@ -189,7 +209,7 @@ lbm_status lbm_coexistence(double Tr, double* rho_v, double* rho_l);
 typedef struct lbm_pool lbm_pool;
 
 /* Create a pool on the current device.  params of submitted requests must use lattice 19,
- * storage 4, edges up to max_edge, no walls and no gravity. */
+ * storage 4, edges up to max_edge, no walls, no gravity and the BGK collision. */
 lbm_status lbm_pool_create(size_t hbm_budget_bytes, int max_slots, int steps_per_run,
                            void* stream, lbm_pool** out);
 

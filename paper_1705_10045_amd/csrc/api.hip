@@ -169,6 +169,12 @@ Phys make_phys(const lbm_params& p)
     ph.T_bottom = p.T_bottom;
     ph.T_top = p.T_top;
     for (int a = 0; a < 3; ++a) ph.g[a] = p.gravity[a];
+    ph.collision = p.collision;
+    const bool mrt = p.collision == LBM_COLLISION_MRT;
+    ph.mrt_de = mrt ? p.s_e - ph.omega : 0.0;
+    ph.mrt_deps = mrt ? p.s_eps - ph.omega : 0.0;
+    ph.mrt_dq = mrt ? p.s_q - ph.omega : 0.0;
+    ph.mrt_dm = mrt ? p.s_m - ph.omega : 0.0;
     return ph;
 }
 
@@ -221,6 +227,15 @@ lbm_status validate_params(const lbm_params* p)
     }
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(p->gravity[a])) { set_error("gravity must be finite"); return LBM_EINVAL; }
+    if (p->collision != LBM_COLLISION_BGK && p->collision != LBM_COLLISION_MRT) {
+        set_error("collision must be LBM_COLLISION_BGK (0) or LBM_COLLISION_MRT (1), got %d", p->collision);
+        return LBM_EINVAL;
+    }
+    if (p->collision == LBM_COLLISION_MRT) {
+        const double r[4] = {p->s_e, p->s_eps, p->s_q, p->s_m};
+        for (int i = 0; i < 4; ++i)
+            if (!(r[i] > 0.0 && r[i] < 2.0)) { set_error("MRT rates must lie in (0, 2)"); return LBM_EINVAL; }
+    }
     // the step addresses nodes within one population plane with 32-bit byte offsets
     const long long n = (long long)p->nx * p->ny * p->nz;
     if ((unsigned long long)padded_plane(n) * (unsigned long long)p->storage_bytes >= (1ull << 32)) {

@@ -220,7 +220,8 @@ hipError_t launch_one(const void* src, void* dst, const StepGeom& g, const Phys&
 }
 
 // Picks the instantiation for the run-time facts: buffer addressing if the state allows it,
-// and the tau = 1 collision (no re-read of N_k) when 1/tau is exactly 1.  Where a variant asks
+// the tau = 1 collision (no re-read of N_k) when 1/tau is exactly 1 with BGK, and the MRT
+// collision (which re-reads N_k, with the load order of tau != 1) when asked for.  Where a variant asks
 // for the LDS stash, it is used where it measured faster on MI355X and fits the registers:
 //   - FP32 with buffer addressing, any tau; the density prefetch stays on for tau = 1 only
 //     (re-reading N_k in the collision leaves no registers for it);
@@ -233,16 +234,19 @@ template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool STAS
 hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Phys& ph,
                          const StepAux& aux, hipStream_t st)
 {
-    const bool tau1 = ph.omega == 1.0;
+    const bool mrt = ph.collision != 0;
+    const bool tau1 = ph.omega == 1.0 && !mrt;
     if constexpr (sizeof(S) == 4 && !GLOBAL) {
         if (fits_buffer(g, Q, 4)) {
-            return tau1 ? launch_one<Q, S, R, TX, TY, NTH, PIPE, STASH, true, kTauOne>(src, dst, g, ph, aux, st)
-                        : launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, true, kTauAny>(src, dst, g, ph, aux, st);
+            if (tau1) return launch_one<Q, S, R, TX, TY, NTH, PIPE, STASH, true, kTauOne>(src, dst, g, ph, aux, st);
+            if (mrt) return launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, true, kMrt>(src, dst, g, ph, aux, st);
+            return launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, true, kTauAny>(src, dst, g, ph, aux, st);
         }
     }
     constexpr bool kStashAnyTau = STASH && sizeof(S) == 4;
-    return tau1 ? launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, false, kTauOne>(src, dst, g, ph, aux, st)
-                : launch_one<Q, S, R, TX, TY, NTH, PIPE && !kStashAnyTau, kStashAnyTau, false, kTauAny>(src, dst, g, ph, aux, st);
+    if (tau1) return launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, false, kTauOne>(src, dst, g, ph, aux, st);
+    if (mrt) return launch_one<Q, S, R, TX, TY, NTH, PIPE && !kStashAnyTau, kStashAnyTau, false, kMrt>(src, dst, g, ph, aux, st);
+    return launch_one<Q, S, R, TX, TY, NTH, PIPE && !kStashAnyTau, kStashAnyTau, false, kTauAny>(src, dst, g, ph, aux, st);
 }
 
 }  // namespace
@@ -313,7 +317,10 @@ hipError_t launch_step(int Q, int storage_bytes, int variant, const void* src, v
         default: return hipErrorInvalidValue;
         }
     }
-    if (Q == 9 && storage_bytes == 4) return launch_step_t<9, float, float, 32, 8, 256, true>(src, dst, g, ph, aux, st);
+    // D2Q9 FP32 populations with FP64 arithmetic: in 2D the registers allow it, and FP32
+    // arithmetic tripled the error of the stored-FP32 state alone (u* 9e-6 to 1e-5 against a
+    // floor of 3e-6 on a 100-step slab)
+    if (Q == 9 && storage_bytes == 4) return launch_step_t<9, float, double, 32, 8, 256, true>(src, dst, g, ph, aux, st);
     if (Q == 9 && storage_bytes == 8) return launch_step_t<9, double, double, 32, 8, 256, false>(src, dst, g, ph, aux, st);
     return hipErrorInvalidValue;
 }

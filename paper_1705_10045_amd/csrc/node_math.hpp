@@ -105,6 +105,69 @@ __device__ __forceinline__ R energy_source(R p, R div, R rho, R T, R rm, const R
     return dE;
 }
 
+// Multiple-relaxation-time collision of N_k (section 2 names it beside BGK) on the orthogonal
+// moment bases of Lallemand and Luo 2000 (D2Q9) and d'Humieres et al. 2002 (D3Q19), written as
+// polynomials of the velocity.  The BGK form relaxes every non-conserved moment at omega, so
+// only the moments outside the shear group need a term of their own, with (s_i - omega):
+// D2Q9 e, eps, q_x, q_y; D3Q19 e, eps, q_x, q_y, q_z, pi_xx, pi_ww, m_x, m_y, m_z.
+template <int Q>
+struct MrtRows;
+template <>
+struct MrtRows<9> {
+    static constexpr int N = 4;
+    static constexpr int id[4] = {1, 2, 4, 6};
+};
+template <>
+struct MrtRows<19> {
+    static constexpr int N = 10;
+    static constexpr int id[10] = {1, 2, 4, 6, 8, 10, 12, 16, 17, 18};
+};
+
+// Row i of the basis at direction k (rows of MrtRows only).
+template <int Q>
+__host__ __device__ constexpr double mrt_row(int i, int k)
+{
+    using L = Lattice<Q>;
+    const double x = L::cx[k], y = L::cy[k], z = L::cz[k];
+    const double c2 = x * x + y * y + z * z;
+    if (Q == 9) {
+        switch (i) {
+        case 1: return 3.0 * c2 - 4.0;                         // e
+        case 2: return 4.5 * c2 * c2 - 10.5 * c2 + 4.0;        // eps
+        case 4: return (3.0 * c2 - 5.0) * x;                   // q_x
+        case 6: return (3.0 * c2 - 5.0) * y;                   // q_y
+        default: return 0.0;
+        }
+    }
+    switch (i) {
+    case 1: return 19.0 * c2 - 30.0;                              // e
+    case 2: return (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0;     // eps
+    case 4: return (5.0 * c2 - 9.0) * x;                          // q_x
+    case 6: return (5.0 * c2 - 9.0) * y;                          // q_y
+    case 8: return (5.0 * c2 - 9.0) * z;                          // q_z
+    case 10: return (3.0 * c2 - 5.0) * (3.0 * x * x - c2);        // pi_xx
+    case 12: return (3.0 * c2 - 5.0) * (y * y - z * z);           // pi_ww
+    case 16: return (y * y - z * z) * x;                          // m_x
+    case 17: return (z * z - x * x) * y;                          // m_y
+    case 18: return (x * x - y * y) * z;                          // m_z
+    default: return 0.0;
+    }
+}
+
+// Rate group of row i: 0 e (s_e), 1 eps and pi (s_eps), 2 q (s_q), 3 m (s_m).
+__host__ __device__ constexpr int mrt_group(int i)
+{
+    return i == 1 ? 0 : (i == 2 || i == 10 || i == 12) ? 1 : (i == 4 || i == 6 || i == 8) ? 2 : 3;
+}
+
+template <int Q>
+__host__ __device__ constexpr double mrt_norm2(int i)
+{
+    double s = 0.0;
+    for (int k = 0; k < Q; ++k) s += mrt_row<Q>(i, k) * mrt_row<Q>(i, k);
+    return s;
+}
+
 // Both collisions of one node as linear combinations of the equilibrium polynomials
 // P_k(v) = w_k (1 + 3 c.v + 4.5 (c.v)^2 - 1.5 v^2) (eq:feq):
 //   N'_k = rho P_k(v) - keepN rho P_k(u) + keepN N_k             (eq:lbe, eq:edm)
@@ -114,9 +177,16 @@ __device__ __forceinline__ R energy_source(R p, R div, R rho, R T, R rm, const R
 // the even part of the polynomial); the rest populations close the mass and energy balances in
 // FP64 over the values actually stored (the BGK, EDM and pseudoforce increments sum to zero and
 // dg(1) sums to dE), so rounding of the lattice weights cannot create mass or energy.
-template <int Q, class S, class R, bool WN>
+// With MRT (which re-reads N_k like any tau != 1) the moving N'_k also lose
+// sum_i am_i M_ik over the rows of MrtRows, am_i = (s_i - omega) m_i / |M_i|^2 with m_i the
+// row's moment of N - rho P(u); those terms sum to zero over k, so the rest population still
+// closes the mass balance.
+template <int Q, class S, class R, bool WN, bool MRT = false>
 struct NodeCollision {
+    static_assert(!MRT || WN, "the MRT collision reads N_k");
+    static constexpr int NG = MRT ? MrtRows<Q>::N : 1;
     R ux, uy, uz, vx, vy, vz, base_u, base_v, rho, keepN, nU, gV, gU, gK;
+    R am[NG];
     double sumN, sumG;
 
     __device__ __forceinline__ void setup(R rho_, R E, R ux_, R uy_, R uz_, R Fx, R Fy, R Fz,
@@ -139,6 +209,36 @@ struct NodeCollision {
         sumG = 0.0;
     }
 
+    // MRT: the rows' moments of the non-equilibrium part f_k = N_k - rho P_k(u) over the moving
+    // directions; f_0 = -sum_{k>0} f_k, since both N and rho P(u) sum to rho, so each row
+    // enters with M_ik - M_i0.  Call after setup.
+    __device__ __forceinline__ void mrt_prepare(const R* pk_n, const Phys& ph)
+    {
+        if constexpr (MRT) {
+            using L = Lattice<Q>;
+            using G = MrtRows<Q>;
+            R m[G::N];
+#pragma unroll
+            for (int i = 0; i < G::N; ++i) m[i] = R(0);
+#pragma unroll
+            for (int k = 1; k < Q; ++k) {
+                const R w = R(weight<Q>(k));
+                const R cu = R(L::cx[k]) * ux + R(L::cy[k]) * uy + R(L::cz[k]) * uz;
+                const R P = fma(R(4.5) * w, cu * cu, w * base_u) + R(3) * w * cu;
+                const R f = fma(-rho, P, pk_n[k]);
+#pragma unroll
+                for (int i = 0; i < G::N; ++i) {
+                    const double coef = mrt_row<Q>(G::id[i], k) - mrt_row<Q>(G::id[i], 0);
+                    if (coef != 0.0) m[i] = fma(R(coef), f, m[i]);
+                }
+            }
+            const R d[4] = {R(ph.mrt_de), R(ph.mrt_deps), R(ph.mrt_dq), R(ph.mrt_dm)};
+#pragma unroll
+            for (int i = 0; i < G::N; ++i)
+                am[i] = d[mrt_group(G::id[i])] * m[i] * R(1.0 / mrt_norm2<Q>(G::id[i]));
+        }
+    }
+
     // directions k and opposite<Q>(k) (k < opposite): out = {N'_k, g'_k, N'_-k, g'_-k}
     __device__ __forceinline__ void dir_pair(int k, const R* pk_n, const R* pk_e, S (&out)[4])
     {
@@ -156,6 +256,13 @@ struct NodeCollision {
             const int q = kk[h];
             R nn = rho * Pv[h];
             if constexpr (WN) nn = fma(keepN, pk_n[q], fma(nU, Pu[h], nn));
+            if constexpr (MRT) {
+#pragma unroll
+                for (int i = 0; i < NG; ++i) {
+                    const double coef = mrt_row<Q>(MrtRows<Q>::id[i], q);
+                    if (coef != 0.0) nn = fma(R(-coef), am[i], nn);
+                }
+            }
             const R gn = fma(gK, pk_e[q], fma(gU, Pu[h], gV * Pv[h]));
             const S nn_s = S(nn), gn_s = S(gn);
             sumN += double(nn_s);

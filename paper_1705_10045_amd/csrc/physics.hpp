@@ -26,6 +26,12 @@ struct Phys {
     unsigned wall_heat;           // kWallTBottom | kWallTTop: wall faces held at a temperature
     double T_bottom, T_top;
     double g[3];                  // body force per unit mass
+    // collision of N_k: 0 BGK; 1 multiple relaxation times, with the shear moments at omega
+    // and the other non-conserved groups at their own rates, stored as (rate - omega) for the
+    // energy e, the energy square and fourth-order moments, the energy fluxes q and (D3Q19)
+    // the third-order moments m
+    int collision;
+    double mrt_de, mrt_deps, mrt_dq, mrt_dm;
 };
 
 enum : unsigned { kWallTBottom = 1u, kWallTTop = 2u };

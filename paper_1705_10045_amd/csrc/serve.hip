@@ -315,8 +315,8 @@ lbm_status lbm_pool_submit(lbm_pool* p, const lbm_params* params, const double* 
         return LBM_EINVAL;
     }
     if (params->walls || params->gravity[0] != 0.0 || params->gravity[1] != 0.0 ||
-        params->gravity[2] != 0.0) {
-        set_error("pool requests are periodic boxes without gravity");
+        params->gravity[2] != 0.0 || params->collision != LBM_COLLISION_BGK) {
+        set_error("pool requests are periodic boxes without gravity, with the BGK collision");
         return LBM_EINVAL;
     }
     st = validate_fields(*params, rho0, u0, T0);

@@ -136,8 +136,9 @@ struct PopIO<float, true> {
 // How the collision treats the density populations: with tau = 1 the BGK term of N' no longer
 // depends on N_k (N' = Neq(rho, u + du) exactly), so they need not be re-read.
 enum NMode : int {
-    kTauOne = 0,  // caller guarantees tau = 1
-    kTauAny = 1   // re-read N_k
+    kTauOne = 0,  // caller guarantees tau = 1 and BGK
+    kTauAny = 1,  // BGK, re-read N_k
+    kMrt = 2      // multiple relaxation times, re-read N_k
 };
 
 // LDS of one workgroup's tile: the rings of the three stages and the stash.  The caller owns it
@@ -440,7 +441,7 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
         if (bb_lo || bb_hi) pulls(std::true_type{});
         else pulls(std::false_type{});
     };
-    using WithN = std::integral_constant<bool, NMODE == kTauAny>;
+    using WithN = std::integral_constant<bool, NMODE != kTauOne>;
 
     // energy source and both collisions of the own node at plane zc; stores the result
     auto collide = [&](int zc, auto with_n) {
@@ -483,9 +484,10 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
         const R dE = energy_source<D, R, FX>(p, div, rho, T, rzm, sRho[sc], rzp, tzm, sT[sc], tzp,
                                              of, cond_half, flags, ph, aux);
 
-        NodeCollision<Q, S, R, WN> c;
+        NodeCollision<Q, S, R, WN, NMODE == kMrt> c;
         c.setup(rho, E, ux, uy, uz, Fo[0], Fo[1], Fo[2], inv_rho, dE, keepN, keepG, omega_E,
                 pseudo);
+        c.mrt_prepare(pk_n, ph);
 #pragma unroll
         for (int k = 1; k < Q; ++k) {
             const int ko = opposite<Q>(k);

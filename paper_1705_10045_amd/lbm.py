@@ -40,8 +40,14 @@ class lbm_params(ctypes.Structure):
         ("walls", ctypes.c_int), ("wall_heat", ctypes.c_uint),
         ("T_bottom", ctypes.c_double), ("T_top", ctypes.c_double),
         ("gravity", ctypes.c_double * 3),
+        ("collision", ctypes.c_int),
+        ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double), ("s_q", ctypes.c_double),
+        ("s_m", ctypes.c_double),
     ]
 
+
+LBM_COLLISION_BGK = 0
+LBM_COLLISION_MRT = 1
 
 LBM_WALL_T_BOTTOM = 1
 LBM_WALL_T_TOP = 2
@@ -133,6 +139,10 @@ def make_params(Q, shape, physics, storage_bytes=4):
     gv = physics.get("gravity", (0.0, 0.0, 0.0))
     for a in range(3):
         p.gravity[a] = float(gv[a])
+    # the collision form is optional too (default BGK; the MRT rates matter only with MRT)
+    p.collision = int(physics.get("collision", LBM_COLLISION_BGK))
+    for k in ("s_e", "s_eps", "s_q", "s_m"):
+        setattr(p, k, float(physics.get(k, 1.0)))
     return p
 
 

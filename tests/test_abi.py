@@ -129,11 +129,15 @@ def test_init_rejects_a_population_plane_over_4gb():
     (dict(walls=1, wall_heat=1, T_bottom=0.8, chi=0.15), "1/(2d + 1)"),
     (dict(walls=1, wall_heat=2, T_top=-1.0), "held wall temperature"),
     (dict(gravity=(0.0, float("nan"), 0.0)), "gravity must be finite"),
+    (dict(collision=2), "collision must be"),
+    (dict(collision=1, s_e=2.0), "MRT rates"),
+    (dict(collision=1, s_q=0.0), "MRT rates"),
 ])
-def test_init_rejects_bad_walls_and_body_force(change, message):
-    """Wall and body-force parameters are validated before any field is read or any device is
-    touched: walls other than 0/1, chi too large next to a held wall (its face is half a cell
-    away), a non-positive held wall temperature, a non-finite gravity."""
+def test_init_rejects_bad_walls_body_force_and_collision(change, message):
+    """Wall, body-force and collision parameters are validated before any field is read or any
+    device is touched: walls other than 0/1, chi too large next to a held wall (its face is half
+    a cell away), a non-positive held wall temperature, a non-finite gravity, an unknown
+    collision, an MRT rate outside (0, 2)."""
     phys, rho, u, T = _case()
     phys = dict(phys, **change)
     p = lbm.make_params(19, (8, 6, 5), phys, storage_bytes=4)

@@ -1,0 +1,117 @@
+"""GPU parity of the multiple-relaxation-time collision (section 2 names it beside BGK) against
+the FP64 oracle, through the C ABI.
+
+The rates are d'Humieres' D3Q19 set (s_e 1.19, s_eps 1.4, s_q 1.2, s_m 1.98) around a shear
+rate 1/tau.  Tolerances as for BGK: 1e-5 relative max-norm for FP32 storage, 1e-11 for FP64,
+after 100 steps.  Also: tau = 1 with MRT must not take the tau = 1 BGK shortcut, equal rates
+reproduce BGK, every launch variant gives bitwise identical fields, walls work with MRT, the
+benchmark size runs in its default MRT launch, and the serving pool refuses MRT requests.
+"""
+import numpy as np
+import pytest
+
+from paper_1705_10045_amd import inputs as I
+from paper_1705_10045_amd import lbm
+
+from parity import compare, describe, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = {4: 1e-5, 8: 1e-11}
+RATES = dict(collision=lbm.LBM_COLLISION_MRT, s_e=1.19, s_eps=1.4, s_q=1.2, s_m=1.98)
+
+
+def mrt(case, **extra):
+    case = dict(case)
+    case["params"] = dict(case["params"], **RATES, **extra)
+    return case
+
+
+def droplet(shape=(28, 36, 40), radius=8.0, **phys):
+    return I.droplet_3d(shape=shape, radius=radius, params=I.physics(**phys))
+
+
+@pytest.mark.parametrize("tau", [0.8, 1.0])
+@pytest.mark.parametrize("storage", [4, 8])
+def test_d3q19_droplet_mrt_100_steps(storage, tau):
+    errs, *_ = compare(mrt(droplet(tau=tau)), 100, storage)
+    describe("D3Q19 droplet MRT tau %.1f %dB" % (tau, storage), errs)
+    assert max(errs.values()) < TOL[storage]
+
+
+@pytest.mark.parametrize("storage", [4, 8])
+def test_d2q9_slab_mrt_100_steps(storage):
+    case = I.slab_2d(n=96, width=30, params=I.physics(tau=0.9))
+    errs, *_ = compare(mrt(case), 100, storage)
+    describe("D2Q9 slab MRT %dB" % storage, errs)
+    assert max(errs.values()) < TOL[storage]
+
+
+@pytest.mark.parametrize("storage", [4, 8])
+def test_pool_boiling_with_mrt_100_steps(storage):
+    case = I.pool_boiling_3d(shape=(30, 20, 24), gravity=1e-4, params=I.physics(tau=0.8))
+    errs, *_ = compare(mrt(case), 100, storage)
+    describe("pool boiling MRT %dB" % storage, errs)
+    assert max(errs.values()) < TOL[storage]
+
+
+def test_equal_rates_reproduce_bgk():
+    tau = 0.8
+    base = droplet(tau=tau)
+    same = mrt(base)
+    same["params"].update(s_e=1 / tau, s_eps=1 / tau, s_q=1 / tau, s_m=1 / tau)
+    a, _ = run_gpu(base, 60, 8)
+    b, _ = run_gpu(same, 60, 8)
+    for k in a:
+        scale = max(np.abs(a[k]).max(), 0.01)
+        assert np.abs(a[k] - b[k]).max() < 1e-12 * scale, k
+
+
+@pytest.mark.parametrize("storage", [4, 8])
+def test_mrt_launch_variants_are_bitwise_identical(storage):
+    case = mrt(droplet(shape=(21, 30, 45), radius=6.0, tau=0.8))
+    ref = None
+    with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"],
+                 storage_bytes=storage) as s:
+        ck = s.checkpoint()
+        v = 0
+        while True:
+            for chunk in (0, 5):
+                try:
+                    s.set_launch(v, chunk)
+                except lbm.LbmError:
+                    assert v > 0 and chunk == 0
+                    break
+                s.restore(ck)
+                s.step(12)
+                m = s.moments()
+                if ref is None:
+                    ref = m
+                for k in m:
+                    assert np.array_equal(m[k], ref[k]), (v, chunk, k)
+            else:
+                v += 1
+                continue
+            break
+    assert v >= 4
+
+
+def test_mrt_128_in_its_default_launch():
+    """The 128^3 droplet workload with MRT in its default launch, every field against the
+    oracle after 10 steps."""
+    case = mrt(I.droplet_3d(n=128), tau=0.8)
+    errs, *_ = compare(case, 10, 4)
+    describe("droplet 128^3 MRT 4B, 10 steps", errs)
+    assert max(errs.values()) < TOL[4]
+
+
+def test_pool_refuses_mrt_requests():
+    case = mrt(I.droplet_3d(shape=(16, 16, 16), radius=4.0))
+    pool = lbm.Pool(1 << 28, max_slots=2, steps_per_run=5)
+    try:
+        with pytest.raises(lbm.LbmError) as e:
+            pool.submit(case["params"], case["rho0"], case["u0"], case["T0"], 10)
+        assert e.value.status == lbm.LBM_EINVAL
+        assert "BGK" in lbm.lbm_last_error()
+    finally:
+        pool.close()

