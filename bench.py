@@ -18,7 +18,7 @@ Prints ONE JSON line:
   cpu_baseline - the FP64 CPU oracle timed on the host cores on a bounded sample (a few steps
               of the same 128^3 workload).
 
---gpus N with N > 1 exits: this build runs on one GPU.
+--gpus N with N > 1 exits: the library runs on one GPU.
 """
 import argparse
 import hashlib
@@ -298,7 +298,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (asked for %d)"
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (asked for %d)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
