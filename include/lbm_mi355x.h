@@ -178,8 +178,9 @@ const char* lbm_last_error(void);
 lbm_status lbm_launch_info(const lbm_sim* sim, int info[4]);
 
 /* Select the launch variant of the fused step kernel (0 .. n-1: tile shape, threads per
- * workgroup, prefetch or LDS stash; D3Q19 has several in each precision, D2Q9 one; 0 is the
- * default) and the z-chunk length (0 = automatic).  Results do not depend on the choice (the
+ * workgroup, prefetch or LDS stash; D3Q19 has seven with FP32 populations and four with FP64,
+ * D2Q9 three: 32x8, 32x16 and 64x8 tiles) and the z-chunk length (0 = automatic).  The default
+ * is variant 0, except 2 for D2Q9 FP32 boxes of 2^19 nodes and more.  Results do not depend on the choice (the
  * per-node arithmetic is the same); only speed does.  LBM_EINVAL for an unknown variant or a
  * negative chunk. */
 lbm_status lbm_set_launch(lbm_sim* sim, int variant, int chunk);

@@ -425,6 +425,10 @@ lbm_status lbm_init(const lbm_params* params, const double* rho0, const double* 
         if (e != hipSuccess) { delete s; return hip_fail(e, "hipStreamCreate"); }
         s->own_stream = true;
     }
+    // D2Q9 FP32 boxes of 2^19 nodes and more start on 64x8 tiles (512 threads): 5-12% faster
+    // than 32x8 at 1000^2, equal at 500^2, slower on small boxes (fewer workgroups)
+    if (s->p.lattice == 9 && s->p.storage_bytes == 4 && (long long)s->p.nx * s->p.ny >= (1LL << 19))
+        s->variant = 2;
     choose_geometry(s, 0);
     const size_t bytes = state_bytes(s->p);
     hipError_t e = hipMalloc(&s->buf[0], bytes);

@@ -251,8 +251,8 @@ hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Ph
 
 }  // namespace
 
-// Launch shapes of the fused step.  Variant 0 is the default per (lattice, storage); the others
-// exist for D3Q19 (the bandwidth-critical paths) and are selected for tuning.  Tile shape,
+// Launch shapes of the fused step.  Variant 0 is the default per (lattice, storage), except
+// for large D2Q9 FP32 boxes (variant 2, chosen at init); the others are selected for tuning.  Tile shape,
 // thread count and the order of the loads do not change the per-node arithmetic, so every
 // variant gives bitwise-identical results.
 // `per_cu` is the number of workgroups of the variant resident per compute unit (set by its
@@ -270,11 +270,16 @@ static const TileShape kVariants19d[] = {
     {32, 8, 512, false, true, 1}, {32, 8, 512, false, false, 1}, {32, 8, 256, false, false, 1},
     {32, 4, 128, false, false, 2}};
 constexpr int kNumVariants19d = sizeof(kVariants19d) / sizeof(kVariants19d[0]);
+// D2Q9 (one plane, no z march): the moment stage pulls the tile plus a 2-node halo, 1.69x the
+// tile's nodes on 32x8 and 1.41x on 32x16
+static const TileShape kVariants9[] = {
+    {32, 8, 256, true, false, 2}, {32, 16, 512, true, false, 1}, {64, 8, 512, true, false, 1}};
+constexpr int kNumVariants9 = sizeof(kVariants9) / sizeof(kVariants9[0]);
 
 int step_variants(int Q, int storage_bytes)
 {
     if (Q == 19) return storage_bytes == 4 ? kNumVariants19f : kNumVariants19d;
-    return 1;
+    return kNumVariants9;
 }
 
 void step_tile(int Q, int storage_bytes, int variant, int& tx, int& ty, int& per_cu)
@@ -282,6 +287,7 @@ void step_tile(int Q, int storage_bytes, int variant, int& tx, int& ty, int& per
     const TileShape* t = nullptr;
     if (Q == 19 && storage_bytes == 4 && variant >= 0 && variant < kNumVariants19f) t = &kVariants19f[variant];
     if (Q == 19 && storage_bytes == 8 && variant >= 0 && variant < kNumVariants19d) t = &kVariants19d[variant];
+    if (Q == 9 && variant >= 0 && variant < kNumVariants9) t = &kVariants9[variant];
     if (t) {
         tx = t->tx;
         ty = t->ty;
@@ -320,8 +326,22 @@ hipError_t launch_step(int Q, int storage_bytes, int variant, const void* src, v
     // D2Q9 FP32 populations with FP64 arithmetic: in 2D the registers allow it, and FP32
     // arithmetic tripled the error of the stored-FP32 state alone (u* 9e-6 to 1e-5 against a
     // floor of 3e-6 on a 100-step slab)
-    if (Q == 9 && storage_bytes == 4) return launch_step_t<9, float, double, 32, 8, 256, true>(src, dst, g, ph, aux, st);
-    if (Q == 9 && storage_bytes == 8) return launch_step_t<9, double, double, 32, 8, 256, false>(src, dst, g, ph, aux, st);
+    if (Q == 9 && storage_bytes == 4) {
+        switch (variant) {
+        case 0: return launch_step_t<9, float, double, 32, 8, 256, true>(src, dst, g, ph, aux, st);
+        case 1: return launch_step_t<9, float, double, 32, 16, 512, true>(src, dst, g, ph, aux, st);
+        case 2: return launch_step_t<9, float, double, 64, 8, 512, true>(src, dst, g, ph, aux, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (Q == 9 && storage_bytes == 8) {
+        switch (variant) {
+        case 0: return launch_step_t<9, double, double, 32, 8, 256, false>(src, dst, g, ph, aux, st);
+        case 1: return launch_step_t<9, double, double, 32, 16, 512, false>(src, dst, g, ph, aux, st);
+        case 2: return launch_step_t<9, double, double, 64, 8, 512, false>(src, dst, g, ph, aux, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     return hipErrorInvalidValue;
 }
 
