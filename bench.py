@@ -16,7 +16,8 @@ Prints ONE JSON line:
               p50/p99 time-to-result under a Poisson stream at 0.8x the burst capacity,
               aggregate MLUPS batched and one at a time (skip with --no-serving);
   cpu_baseline - the FP64 CPU oracle timed on the host cores on a bounded sample (a few steps
-              of the same 128^3 workload).
+              of the same 128^3 workload), and the library's fields after the same steps in
+              the timed launch compared with the oracle's (parity_vs_gpu).
 
 --gpus N with N > 1 exits: the library runs on one GPU.
 """
@@ -106,9 +107,16 @@ def measured_traffic(config_name, bytes_alg):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(case, budget_s=12.0):
-    """The oracle as it stands, on the host cores, over whole steps of the same workload."""
+PARITY_TOL = {4: 1e-5, 8: 1e-11}
+
+
+def cpu_baseline(case, storage=4, launch=None, budget_s=12.0):
+    """The oracle as it stands, on the host cores, over whole steps of the same workload.  The
+    state it reaches is then compared with the library's after the same steps from the same
+    initial fields, in the launch the benchmark times (relative max-norm per field; u* relative
+    to max(|u*|, 0.01))."""
     import oracle
+    from paper_1705_10045_amd import lbm
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     s = oracle.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"])
     n = case["rho0"].size
@@ -120,11 +128,25 @@ def cpu_baseline(case, budget_s=12.0):
         el = time.perf_counter() - t0
         if el > budget_s or steps >= 50:
             break
+    ref = s.moments()
     s.close()
+    with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"],
+                 storage_bytes=storage) as g:
+        if launch is not None:
+            g.set_launch(*launch)
+        g.step(steps)
+        got = g.moments()
+    errs = {}
+    for k in ("rho", "u_star", "E", "T"):
+        scale = max(float(abs(ref[k]).max()), 0.01 if k == "u_star" else 0.0)
+        errs[k] = float("%.3g" % (abs(got[k] - ref[k]).max() / scale))
     return {"value": round(n * steps / el / 1e6, 3), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
             "sample": "%d whole FP64 steps of the same %s workload (%.1f s)" %
-                      (steps, "x".join(str(d) for d in case["rho0"].shape[::-1]), el)}
+                      (steps, "x".join(str(d) for d in case["rho0"].shape[::-1]), el),
+            "parity_vs_gpu": {"steps": steps, "max_rel_err": errs,
+                              "tolerance": PARITY_TOL[storage],
+                              "pass": max(errs.values()) < PARITY_TOL[storage]}}
 
 
 def copy_probe(gib=1.0, reps=5):
@@ -375,7 +397,8 @@ def main():
     if not args.no_serving:
         out["serving"] = serving_bench(count=args.serving_requests)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case)
+        launch = (args.variant or 0, args.chunk) if (args.variant is not None or args.chunk) else None
+        out["cpu_baseline"] = cpu_baseline(case, storage, launch)
     print(json.dumps(out), flush=True)
 
 
