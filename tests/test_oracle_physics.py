@@ -293,3 +293,29 @@ def test_latent_heat_released_where_fluid_condenses(orc):
     m = (lat != 0) & (np.abs(d) > 1e-3 * np.abs(d).max())
     assert m.sum() > 20
     assert np.mean(np.sign(lat[m]) == np.sign(d[m])) > 0.9
+
+
+def test_stepwise_hot_layer_needs_tau_e_above_0_503_without_conduction(orc):
+    """The Fig. 4a state (stepwise T and rho at equal pressure) with the paper's tau_E = 0.503
+    and no conduction leaves the EOS domain within 1000 steps: the temperature couples through
+    the pressure into a growing short wave.  tau_E = 0.51 runs 1500 steps and keeps T inside
+    its initial range; so do a temperature-independent (barotropic) pressure at 0.503 and
+    chi = 0.1 at 0.503.  The paper-scale runs of Figs. 5 and 6 therefore use tau_E = 0.51."""
+    import scenarios as S
+
+    def run(steps, **kw):
+        baro = kw.pop("baro", False)
+        case = S.hot_gas_1d(**kw)
+        p = dict(case["params"])
+        if baro:
+            p.update(flags=I.BAROTROPIC | I.PSEUDOFORCE, T0_baro=0.6)
+        s = orc.Sim(9, p, case["rho0"], case["u0"], case["T0"])
+        s.step(steps)
+        return s.moments()["T"]
+
+    with pytest.raises(FloatingPointError):
+        run(1000, tau_E=0.503, chi=0.0)
+    for kw in (dict(tau_E=0.51, chi=0.0), dict(tau_E=0.503, chi=0.1),
+               dict(tau_E=0.503, chi=0.0, baro=True)):
+        T = run(1500, **kw)
+        assert T.min() > 0.59 and T.max() < 0.96, kw
