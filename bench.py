@@ -34,7 +34,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (coupled density+energy) & % HBM roofline, 1 GPU; serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_UPDATE = {4: 2 * 19 * 2 * 4, 8: 2 * 19 * 2 * 8}
+BYTES_PER_UPDATE = {4: 2 * 19 * 2 * 4, 8: 2 * 19 * 2 * 8}   # D3Q19
+
+
+def bytes_per_update(Q, storage):
+    """Algorithmic bytes of one node update: both population sets read once and written once."""
+    return 2 * Q * 2 * storage
 KERNEL_SOURCES = ["paper_1705_10045_amd/csrc/step_kernel.hpp", "paper_1705_10045_amd/csrc/node_math.hpp",
                   "paper_1705_10045_amd/csrc/physics.hpp",
                   "paper_1705_10045_amd/csrc/lattice.hpp", "paper_1705_10045_amd/csrc/kernels.hip",
@@ -80,6 +85,22 @@ def workload(name):
         return case, 4, {"workload": "d3q19_spinodal_512^3_fp32", "lattice": "D3Q19",
                          "shape": [512, 512, 512], "storage": "fp32", "T_over_Tc": 0.75,
                          "rho_mean": 1.0, "noise_sigma": 0.02,
+                         "terms": "work+conduction+latent+pseudoforces"}
+    if name == "droplet128_mrt":
+        case = I.droplet_3d(n=128, radius=24.0, Tr=0.8, noise=0.005, velocity=(0.05, 0.0, 0.0),
+                            params=I.physics(tau=0.8))
+        rates = dict(collision=1, s_e=1.19, s_eps=1.4, s_q=1.2, s_m=1.98)
+        case["params"] = dict(case["params"], **rates)
+        return case, 4, {"workload": "d3q19_thermal_droplet_128^3_fp32_mrt", "lattice": "D3Q19",
+                         "shape": [128, 128, 128], "storage": "fp32", "T_over_Tc": 0.8,
+                         "radius": 24, "noise": 0.005, "velocity": [0.05, 0.0, 0.0],
+                         "collision": "MRT", "tau": 0.8, "rates": rates,
+                         "terms": "work+conduction+latent+pseudoforces"}
+    if name == "slab1000_d2q9":
+        case = I.slab_2d(n=1000, width=300)
+        return case, 4, {"workload": "d2q9_thermal_slab_1000^2_fp32", "lattice": "D2Q9",
+                         "shape": [1, 1000, 1000], "storage": "fp32 (FP64 arithmetic)",
+                         "T_over_Tc": 0.85, "width": 300, "noise": 0.01,
                          "terms": "work+conduction+latent+pseudoforces"}
     if name in ("poolboil512", "poolboil128"):
         n = 512 if name == "poolboil512" else 128
@@ -374,7 +395,7 @@ def main():
     ms_per_step = ms / args.steps
     mlups = n * args.steps / (ms / 1e3) / 1e6
 
-    bytes_alg = BYTES_PER_UPDATE[storage] * n
+    bytes_alg = bytes_per_update(case["Q"], storage) * n
     achieved = bytes_alg / (ms_per_step / 1e3) / 1e9
     traffic = measured_traffic(config["workload"], bytes_alg)
     totals = sim.reduce()
@@ -389,8 +410,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "lbm::k_step<19,%s> (one launch per step)" %
-                               ("float" if storage == 4 else "double"),
+                     "kernel": "lbm::k_step<%d,%s> (one launch per step)" %
+                               (case["Q"], "float" if storage == 4 else "double"),
                      "algorithmic_bytes_per_launch": bytes_alg},
         "totals_fp64": [float(x) for x in totals],
     }
