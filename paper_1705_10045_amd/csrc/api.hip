@@ -289,12 +289,15 @@ void choose_geometry(lbm_sim* s, int chunk_request)
     g.ntx = (p.nx + tx - 1) / tx;
     g.nty = (p.ny + ty - 1) / ty;
     int chunk = p.nz;
+    // workgroups the device holds at once: the launch runs in rounds of this many, and the
+    // kernel gives each round a contiguous band of tiles
+    g.resident = s->cus * per_cu;
     if (p.lattice == 19) {
-        // about as many workgroups as the 256 compute units hold at once (one round), with the
+        // about as many workgroups as the compute units hold at once (one round), with the
         // longest z chunks that allows: each chunk runs the moment stage on 4 planes outside it
         // (2 on each side), so longer chunks waste less (chunks of at least 4 planes)
         const long long cols = (long long)g.ntx * g.nty;
-        const long long target = 256LL * per_cu;
+        const long long target = (long long)s->cus * per_cu;
         long long want = (target + cols - 1) / cols;
         const long long maxc = p.nz / 4 > 0 ? p.nz / 4 : 1;
         if (want > maxc) want = maxc;
@@ -416,6 +419,11 @@ lbm_status lbm_init(const lbm_params* params, const double* rho0, const double* 
     if (hipError_t e = hipGetDevice(&s->device); e != hipSuccess) {
         delete s;
         return hip_fail(e, "hipGetDevice");
+    }
+    if (hipError_t e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device);
+        e != hipSuccess || s->cus < 1) {
+        delete s;
+        return hip_fail(e == hipSuccess ? hipErrorInvalidDevice : e, "compute unit count");
     }
     if (stream) {
         s->stream = (hipStream_t)stream;

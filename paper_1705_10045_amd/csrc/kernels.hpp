@@ -14,6 +14,7 @@ struct StepGeom {
     int ntx, nty;           // tiles along x and y
     int chunk;              // z planes per workgroup
     int nchunks;
+    int resident;           // workgroups the GPU holds at once (one round), 0 if unknown
 };
 
 // Read-only tables and the error word shared by every step launch of a simulation.

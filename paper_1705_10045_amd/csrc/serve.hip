@@ -190,6 +190,7 @@ StepGeom pool_geometry(const lbm_params& p)
     g.nty = (p.ny + kPoolTY - 1) / kPoolTY;
     g.chunk = kPoolChunk < p.nz ? kPoolChunk : p.nz;
     g.nchunks = (p.nz + g.chunk - 1) / g.chunk;
+    g.resident = 0;
     return g;
 }
 

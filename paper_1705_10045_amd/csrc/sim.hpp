@@ -14,6 +14,7 @@ struct lbm_sim {
     lbm::StepAux aux;
     long long n = 0, plane = 0;
     int device = 0;
+    int cus = 256;                       // compute units of the device
     hipStream_t stream = nullptr;
     bool own_stream = false;
     void* buf[2] = {nullptr, nullptr};  // population buffers; buf[cur] holds the current state

@@ -40,13 +40,23 @@
 
 namespace lbm {
 
-// XCD-aware placement: consecutive workgroups are dealt round-robin to the 8 XCDs, so
-// workgroup b is given logical tile (b % 8) * (nblk / 8) + b / 8.  Each XCD then owns a
-// contiguous run of tiles and their shared halos meet in its own L2.
-__device__ __forceinline__ int xcd_logical_block(int b, int nblk)
+// XCD-aware placement.  Consecutive workgroups are dealt round-robin to the 8 XCDs, and a launch
+// larger than what the GPU holds at once runs in rounds of `resident` workgroups (dispatched in
+// index order as earlier ones retire).  Workgroup b of round r = b / resident is given logical
+// tile r * resident + (b % 8) * (resident / 8) + (b % resident) / 8, so that
+//   - each round covers one contiguous run of tiles (x fastest, then y: a band of tile rows),
+//     and every tile's neighbours inside the band run at the same time as it;
+//   - each XCD owns a contiguous part of that run, and shared halos meet in its own L2.
+// A last round shorter than `resident` is split the same way when it is a multiple of 8 and
+// left in index order otherwise.  resident <= 0 means one round (the whole launch).
+__device__ __forceinline__ int xcd_logical_block(int b, int nblk, int resident = 0)
 {
-    if ((nblk & 7) == 0) return (b & 7) * (nblk >> 3) + (b >> 3);
-    return b;
+    const int R = (resident > 0 && resident < nblk && (resident & 7) == 0) ? resident : nblk;
+    const int base = (b / R) * R;
+    const int cnt = min(R, nblk - base);
+    if ((cnt & 7) != 0) return b;
+    const int l = b - base;
+    return base + (l & 7) * (cnt >> 3) + (l >> 3);
 }
 
 // Interior-first enumeration of a (W+2h) x (H+2h) region around a W x H tile: slots
@@ -110,26 +120,32 @@ struct PopIO<S, false> {
     }
 };
 
+// Offsets are formed in unsigned 32-bit arithmetic (the host allows this form only for states
+// under 4 GB, so no offset wraps) and handed to the builtins as their bit pattern.
 template <>
 struct PopIO<float, true> {
     __amdgpu_buffer_rsrc_t rs, rd;
-    int plane_bytes;
+    unsigned plane_bytes;
     __device__ PopIO(const float* s, float* d, long long p, int npk)
     {
-        const unsigned bytes = (unsigned)(p * npk * 4);
-        rs = __builtin_amdgcn_make_buffer_rsrc((void*)s, (short)0, (int)bytes, 0x00020000);
-        rd = __builtin_amdgcn_make_buffer_rsrc((void*)d, (short)0, (int)bytes, 0x00020000);
-        plane_bytes = (int)(p * 4);
+        const unsigned bytes = (unsigned)((unsigned long long)p * (unsigned)npk * 4u);
+        rs = __builtin_amdgcn_make_buffer_rsrc((void*)s, (short)0, __builtin_bit_cast(int, bytes), 0x00020000);
+        rd = __builtin_amdgcn_make_buffer_rsrc((void*)d, (short)0, __builtin_bit_cast(int, bytes), 0x00020000);
+        plane_bytes = (unsigned)((unsigned long long)p * 4u);
     }
     // cache-policy operand of the buffer instructions: bit 1 is the non-temporal hint
     static constexpr int kNT = 2;
     __device__ __forceinline__ float load(int pk, int i) const
     {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, i * 4, pk * plane_bytes, 0));
+        const int voff = __builtin_bit_cast(int, (unsigned)i * 4u);
+        const int soff = __builtin_bit_cast(int, (unsigned)pk * plane_bytes);
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
     }
     __device__ __forceinline__ void store(int pk, int i, float v) const
     {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rd, i * 4, pk * plane_bytes, kNT);
+        const int voff = __builtin_bit_cast(int, (unsigned)i * 4u);
+        const int soff = __builtin_bit_cast(int, (unsigned)pk * plane_bytes);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rd, voff, soff, kNT);
     }
 };
 
@@ -621,7 +637,7 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const P
 {
     __shared__ TileLds<Q, S, R, TX, TY, STASH> lds;
     step_tile<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, STASH, EXT>(
-        lds, src, dst, g, ph, aux, xcd_logical_block(blockIdx.x, gridDim.x));
+        lds, src, dst, g, ph, aux, xcd_logical_block(blockIdx.x, gridDim.x, g.resident));
 }
 
 }  // namespace lbm

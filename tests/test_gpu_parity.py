@@ -105,15 +105,16 @@ def fp32_storage_floor(case, steps):
 
 @pytest.mark.parametrize("name", ["spinodal", "slab2d"])
 def test_fp32_against_storage_floor(name):
-    """Chaotic or near-critical workloads amplify rounding.  The FP32 error is reported next to
-    the floor set by FP32 storage itself; the GPU must meet 1e-5 or stay within 4x that floor."""
+    """Chaotic or near-critical workloads amplify rounding.  The FP32 error must meet 1e-5; it is
+    reported next to the floor set by FP32 storage itself (the oracle rounded to FP32 after every
+    step), and so is the u* error relative to max|u*| without the 0.01 floor."""
     case = spinodal() if name == "spinodal" else I.slab_2d()
     errs, *_ = compare(case, 100, 4)
     floor = fp32_storage_floor(case, 100)
     describe("%s 4B" % name, errs)
     describe("   FP32-storage floor", floor)
     for k in errs:
-        assert errs[k] < max(1e-5, 4 * floor[k]), k
+        assert errs[k] < 1e-5, k
 
 
 FLAG_SETS = [0, I.WORK, I.CONDUCTION, I.PSEUDOFORCE, I.WORK | I.LATENT | I.PSEUDOFORCE,
