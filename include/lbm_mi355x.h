@@ -141,8 +141,23 @@ lbm_status lbm_check(lbm_sim* sim);
 lbm_status lbm_moments(lbm_sim* sim, double* rho, double* u_star, double* E, double* T);
 
 /* Same as lbm_moments but into caller-owned device FP64 arrays on the simulation's device;
- * enqueued on the simulation's stream (not synchronised). */
+ * enqueued on the simulation's stream (not synchronised).  The first call allocates a moment
+ * scratch of 10 n doubles that the simulation keeps until lbm_free. */
 lbm_status lbm_moments_device(lbm_sim* sim, double* rho, double* u_star, double* E, double* T);
+
+/* lbm_moments_device for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid the allocator).  Same kernels and the
+ * same results, bit for bit, but the scratch (7 n doubles) is a fixed 128 MiB device array of
+ * the library, so the call allocates and frees nothing.  Limit: boxes of at most 2,396,745
+ * nodes (128^3 fits); LBM_EINVAL for larger ones.  Outputs: caller-owned device FP64 arrays of
+ * n values (u_star: 3n) on the simulation's device, any may be NULL; enqueued on the
+ * simulation's stream, not synchronised.  The array is one per GPU, shared by every simulation
+ * on it, and keeps the last call's contents: calls whose work overlaps on one GPU (from other
+ * host threads, or on other streams before the previous call's work has finished) race on it
+ * and give undefined fields; calls ordered on one stream are safe.  Each GPU the library runs
+ * on holds the array until the process ends; the first call on a device looks up its address
+ * there. */
+lbm_status lbm_moments_device_noalloc(lbm_sim* sim, double* rho, double* u_star, double* E, double* T);
 
 /* Totals of the current state accumulated in FP64 with a deterministic reduction order:
  * out[0] = sum N_k (mass), out[1..3] = sum c_k N_k (momentum), out[4] = sum g_k (internal

@@ -65,6 +65,7 @@ _SIGNATURES = [
     ("lbm_check", _ST, [_P]),
     ("lbm_moments", _ST, [_P, _D, _D, _D, _D]),
     ("lbm_moments_device", _ST, [_P, _P, _P, _P, _P]),
+    ("lbm_moments_device_noalloc", _ST, [_P, _P, _P, _P, _P]),
     ("lbm_reduce", _ST, [_P, _D]),
     ("lbm_step_count", ctypes.c_longlong, [_P]),
     ("lbm_footprint_bytes", ctypes.c_size_t, [ctypes.POINTER(lbm_params)]),
@@ -183,6 +184,10 @@ def lbm_moments(h, shape):
 
 def lbm_moments_device(h, rho_ptr, us_ptr, E_ptr, T_ptr):
     return _check(lib().lbm_moments_device(h, rho_ptr, us_ptr, E_ptr, T_ptr))
+
+
+def lbm_moments_device_noalloc(h, rho_ptr, us_ptr, E_ptr, T_ptr):
+    return _check(lib().lbm_moments_device_noalloc(h, rho_ptr, us_ptr, E_ptr, T_ptr))
 
 
 def lbm_reduce(h):
