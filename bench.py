@@ -1,10 +1,13 @@
 """Benchmark of the fused thermal multiphase LBM step on one MI355X.
 
-Default workload: D3Q19 thermal two-phase droplet, 128^3 periodic, FP32 populations, van der
-Waals EOS at T/Tc = 0.8, liquid sphere of radius 24 in vapour with +-0.5% seeded noise, uniform
-velocity (0.05, 0, 0), every physical term on.  The state is resident in HBM before the timed
-region; the timed region is K fused step launches bracketed by HIP events on the simulation's
-stream (torch's current stream, so torch.cuda.Event sees exactly these launches).
+Default workload: D3Q19 pool boiling, 512^3, FP32 populations (40.8 GB of state), van der
+Waals EOS, walls normal to z (bottom held at T/Tc = 0.9, top at 0.7), gravity 1e-5 along -z, a
+liquid layer filling the lower 60% at the coexistence densities of T/Tc = 0.8 with +-1% seeded
+noise, every physical term on: the largest single-GPU configuration of the method's workloads.
+Other workloads (--workload): droplet128 (D3Q19 thermal droplet 128^3 moving at 0.05),
+spinodal256 / spinodal256_fp64, spinodal512, droplet128_mrt, slab1000_d2q9, poolboil128.  The
+state is resident in HBM before the timed region; the timed region is K fused step launches
+bracketed by HIP events recorded on the simulation's own stream.
 
 Prints ONE JSON line:
   value     - node updates per second in millions (MLUPS), one update = both population sets;
@@ -12,12 +15,15 @@ Prints ONE JSON line:
               x 4 B = 304 B per node update, divided by the measured launch duration, against
               the 8 TB/s peak; 'traffic' is the HBM traffic per launch measured by rocprofv3
               counters (profiles/), or null when not measured for the current kernel source;
-  serving   - continuous batching of a stream of uneven requests through the device pool:
-              p50/p99 time-to-result under a Poisson stream at 0.8x the burst capacity,
-              aggregate MLUPS batched and one at a time (skip with --no-serving);
-  cpu_baseline - the FP64 CPU oracle timed on the host cores on a bounded sample (a few steps
-              of the same 128^3 workload), and the library's fields after the same steps in
-              the timed launch compared with the oracle's (parity_vs_gpu).
+  serving   - continuous batching of the stream of uneven requests through the device pool
+              (the first 128 of its 512 requests, listed step counts): p50/p99
+              time-to-result under a Poisson stream at 0.8x the burst capacity, aggregate MLUPS
+              batched and one at a time (skip with --no-serving);
+  cpu_baseline - the FP64 CPU oracle timed on the host cores on a bounded sample: whole steps
+              of the same workload at its full size when the host memory holds the oracle's
+              state (about 0.8 kB per node), else at the largest smaller edge of the same
+              recipe that fits; the library's fields after the same steps, in the launch the
+              benchmark times, compared with the oracle's (parity_vs_gpu).
 
 --gpus N with N > 1 exits: the library runs on one GPU.
 """
@@ -64,8 +70,34 @@ def kernel_source_hash(read=None):
     return h.hexdigest()[:16]
 
 
-def workload(name):
+DEFAULT_WORKLOAD = "poolboil512"
+
+# host bytes per node the FP64 oracle holds (4 population arrays of 19 doubles and 24 field
+# doubles), plus the initial fields and the two sets of output moments of the comparison
+ORACLE_BYTES_PER_NODE = 4 * 19 * 8 + 24 * 8 + 3 * 6 * 8
+HOST_CAP_BYTES = 200e9
+
+
+def host_available_bytes():
+    """MemAvailable of the host, in bytes (0 if unknown)."""
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemAvailable:"):
+                    return int(line.split()[1]) * 1024
+    except OSError:
+        pass
+    return 0
+
+
+def workload(name, edge=None):
+    """(case, storage bytes, config) of a named workload; `edge` rebuilds the same recipe on a
+    smaller cube (the CPU baseline's fallback when the host cannot hold the full size)."""
     from paper_1705_10045_amd import inputs as I
+    if edge is not None:
+        for family in ("poolboil", "spinodal"):
+            if name.startswith(family) and name[len(family):].isdigit():
+                name = "%s%d" % (family, edge)
     if name == "droplet128":
         case = I.droplet_3d(n=128, radius=24.0, Tr=0.8, noise=0.005, velocity=(0.05, 0.0, 0.0))
         return case, 4, {"workload": "d3q19_thermal_droplet_128^3_fp32", "lattice": "D3Q19",
@@ -80,10 +112,11 @@ def workload(name):
                                "storage": "fp64" if storage == 8 else "fp32", "T_over_Tc": 0.75,
                                "rho_mean": 1.0, "noise_sigma": 0.02,
                                "terms": "work+conduction+latent+pseudoforces"}
-    if name == "spinodal512":
-        case = I.spinodal_3d(n=512, Tr=0.75, rho_mean=1.0, sigma=0.02)
-        return case, 4, {"workload": "d3q19_spinodal_512^3_fp32", "lattice": "D3Q19",
-                         "shape": [512, 512, 512], "storage": "fp32", "T_over_Tc": 0.75,
+    if name.startswith("spinodal") and name[len("spinodal"):].isdigit():
+        n = int(name[len("spinodal"):])
+        case = I.spinodal_3d(n=n, Tr=0.75, rho_mean=1.0, sigma=0.02)
+        return case, 4, {"workload": "d3q19_spinodal_%d^3_fp32" % n, "lattice": "D3Q19",
+                         "shape": [n, n, n], "storage": "fp32", "T_over_Tc": 0.75,
                          "rho_mean": 1.0, "noise_sigma": 0.02,
                          "terms": "work+conduction+latent+pseudoforces"}
     if name == "droplet128_mrt":
@@ -102,8 +135,8 @@ def workload(name):
                          "shape": [1, 1000, 1000], "storage": "fp32 (FP64 arithmetic)",
                          "T_over_Tc": 0.85, "width": 300, "noise": 0.01,
                          "terms": "work+conduction+latent+pseudoforces"}
-    if name in ("poolboil512", "poolboil128"):
-        n = 512 if name == "poolboil512" else 128
+    if name.startswith("poolboil") and name[len("poolboil"):].isdigit():
+        n = int(name[len("poolboil"):])
         case = I.pool_boiling_3d(n=n)
         pp = case["params"]
         return case, 4, {"workload": "d3q19_pool_boiling_%d^3_fp32" % n, "lattice": "D3Q19",
@@ -131,26 +164,47 @@ def measured_traffic(config_name, bytes_alg):
 PARITY_TOL = {4: 1e-5, 8: 1e-11}
 
 
-def cpu_baseline(case, storage=4, launch=None, budget_s=12.0):
-    """The oracle as it stands, on the host cores, over whole steps of the same workload.  The
-    state it reaches is then compared with the library's after the same steps from the same
-    initial fields, in the launch the benchmark times (relative max-norm per field; u* relative
-    to max(|u*|, 0.01))."""
+def cpu_baseline(name, case, storage=4, launch=None, budget_s=20.0, max_steps=50, log=None):
+    """The oracle as it stands, on the host cores, over whole steps of the same workload: at its
+    full size when the host's available memory holds the oracle's state with room to spare,
+    else the same recipe on the largest smaller cube that fits (the sample says which).  At
+    least one step; more while the steps taken so far stay under `budget_s`.  The state it
+    reaches is then compared with the library's after the same steps from the same initial
+    fields, in the launch the benchmark times (relative max-norm per field; u* relative to
+    max(|u*|, 0.01), and without that floor as u_star_unfloored)."""
+    import numpy as np
     import oracle
     from paper_1705_10045_amd import lbm
+    log = log or (lambda msg: print(msg, file=sys.stderr, flush=True))
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    s = oracle.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"])
+    avail = host_available_bytes()
+    # at most half of what is available, and never more than HOST_CAP_BYTES
+    room = min(0.5 * avail, HOST_CAP_BYTES) if avail else HOST_CAP_BYTES
+    n_full = case["rho0"].size
+    edge = None
+    if n_full * ORACLE_BYTES_PER_NODE > room:
+        e = case["rho0"].shape[0]
+        while e > 32 and (e ** 3) * ORACLE_BYTES_PER_NODE > room:
+            e //= 2
+        edge = e
+        case, _, _ = workload(name, edge)
     n = case["rho0"].size
+    size = "x".join(str(d) for d in case["rho0"].shape[::-1])
+    log("cpu_baseline: oracle on %s (%s, %.0f GB available)" %
+        (size, "full size" if edge is None else "reduced from the full size", avail / 1e9))
+    s = oracle.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"])
     steps = 0
     t0 = time.perf_counter()
     while True:
         s.step(1)
         steps += 1
         el = time.perf_counter() - t0
-        if el > budget_s or steps >= 50:
+        log("cpu_baseline: oracle step %d done (%.1f s)" % (steps, el))
+        if el * (steps + 1) / steps > budget_s or steps >= max_steps:
             break
     ref = s.moments()
     s.close()
+    log("cpu_baseline: the library on the same fields")
     with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"],
                  storage_bytes=storage) as g:
         if launch is not None:
@@ -159,13 +213,18 @@ def cpu_baseline(case, storage=4, launch=None, budget_s=12.0):
         got = g.moments()
     errs = {}
     for k in ("rho", "u_star", "E", "T"):
-        scale = max(float(abs(ref[k]).max()), 0.01 if k == "u_star" else 0.0)
-        errs[k] = float("%.3g" % (abs(got[k] - ref[k]).max() / scale))
+        scale = max(float(np.abs(ref[k]).max()), 0.01 if k == "u_star" else 0.0)
+        errs[k] = float("%.3g" % (np.abs(got[k] - ref[k]).max() / scale))
+    raw = float(np.abs(got["u_star"] - ref["u_star"]).max() / max(np.abs(ref["u_star"]).max(), 1e-300))
+    del ref, got
     return {"value": round(n * steps / el / 1e6, 3), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
-            "sample": "%d whole FP64 steps of the same %s workload (%.1f s)" %
-                      (steps, "x".join(str(d) for d in case["rho0"].shape[::-1]), el),
-            "parity_vs_gpu": {"steps": steps, "max_rel_err": errs,
+            "sample": "%d whole FP64 step%s of the same workload on %s%s (%.1f s)" %
+                      (steps, "" if steps == 1 else "s", size,
+                       "" if edge is None else " (the full size needs more host memory than the "
+                       "%.0f GB allowed)" % (room / 1e9), el),
+            "parity_vs_gpu": {"steps": steps, "size": size, "max_rel_err": errs,
+                              "u_star_unfloored": float("%.3g" % raw),
                               "tolerance": PARITY_TOL[storage],
                               "pass": max(errs.values()) < PARITY_TOL[storage]}}
 
@@ -183,14 +242,26 @@ def copy_probe(gib=1.0, reps=5):
                       "launches": reps}), flush=True)
 
 
-def copy_ceiling(edges=(128, 256), reps=20):
-    """Bandwidth of a plain device copy of the step's state (2 x 19 float arrays), timed with
-    events: the practical ceiling of an access pattern that reads and writes every population
-    once."""
+def copy_ceiling(edges=(128, 256, 512), reps=20):
+    """Bandwidth of plain device copies of the step's state (2 x 19 float arrays of edge^3
+    nodes): torch's copy, and the HIP probe (libceiling.so) in two orders, the state as one
+    flat array and all 38 planes of a run of nodes together (the step's order).  Events time
+    `reps` copies after a warm-up.  This is the practical ceiling of a pattern that reads and
+    writes every population once."""
+    import ctypes
     import torch
+    from paper_1705_10045_amd import build as lib_build
+    if not os.path.exists(lib_build.PROBE_LIB):
+        lib_build.build()
+    probe = ctypes.CDLL(lib_build.PROBE_LIB)
+    probe.lbm_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_float)]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
     out = {}
     for edge in edges:
-        m = 38 * edge ** 3
+        n = edge ** 3
+        m = 38 * n
         a = torch.ones(m, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         for _ in range(3):
@@ -203,23 +274,44 @@ def copy_ceiling(edges=(128, 256), reps=20):
             b.copy_(a)
         end.record()
         torch.cuda.synchronize()
-        ms = start.elapsed_time(end) / reps
-        out["state_copy_%d" % edge] = {"ms": round(ms, 4), "GB_per_s": round(2 * 4 * m / ms / 1e6, 1),
-                                       "mlups_equivalent": round(edge ** 3 / ms / 1e3, 1)}
+        res = {"torch_copy": start.elapsed_time(end) / reps}
+        for name, order in (("hip_flat", 0), ("hip_sweep", 1)):
+            best = None
+            for per_cu in (4, 8, 16):
+                ms = ctypes.c_float()
+                st = probe.lbm_probe_copy(a.data_ptr(), b.data_ptr(), n, 38, order, reps,
+                                          cus * per_cu, ctypes.byref(ms))
+                if st != 0:
+                    raise RuntimeError("lbm_probe_copy failed (%d)" % st)
+                if best is None or ms.value < best[0]:
+                    best = (ms.value, cus * per_cu)
+            res[name] = best[0]
+            res[name + "_workgroups"] = best[1]
+        out["state_copy_%d" % edge] = {
+            k: (round(v, 4) if not k.endswith("workgroups") else v) for k, v in res.items()}
+        for k in ("torch_copy", "hip_flat", "hip_sweep"):
+            out["state_copy_%d" % edge][k + "_GB_per_s"] = round(2 * 4 * m / res[k] / 1e6, 1)
+        print(json.dumps({"edge": edge, **out["state_copy_%d" % edge]}), file=sys.stderr, flush=True)
         del a, b
+        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 
-def serving_bench(count=48, steps_range=(100, 1000), budget_gib=4.0, max_slots=64,
-                  steps_per_run=20, load=0.8):
-    """Continuous-batching serving of a stream of uneven D3Q19 FP32 requests (edges 32..128,
-    droplet or slab, T/Tc in [0.70, 0.95], +-1% noise; step counts scaled down from the
-    500..5000 of the full request mix so the run stays short).  Three passes over the same
-    request list: a burst (all arrive at t = 0) measures the batched capacity; a Poisson stream
-    offered at `load` x that capacity gives p50/p99 time-to-result; the same requests one after
-    another with a single simulation each give the one-at-a-time rate.  Each request carries its
-    initial fields (built before the clock starts); upload, initialisation, the steps and the
-    download of the result fields are timed."""
+SERVING_STREAM = 512          # requests in the listed serving stream
+SERVING_DEFAULT_COUNT = 128   # the benchmark line's cut of it (the first requests, as listed)
+
+
+def serving_bench(count=SERVING_DEFAULT_COUNT, steps_range=(500, 5000), budget_gib=64.0,
+                  max_slots=64, steps_per_run=20, load=0.8):
+    """Continuous-batching serving of the stream of uneven D3Q19 FP32 requests (edges
+    32..128, droplet or slab, T/Tc in [0.70, 0.95], +-1% noise, 500..5000 steps): the first
+    `count` requests of the 512-request stream, each with its listed step count (request i
+    does not depend on the count).  Three passes over the same request list: a burst (all
+    arrive at t = 0) measures the batched capacity; a Poisson stream offered at `load` x that
+    capacity gives p50/p99 time-to-result; the same requests one after another with a single
+    simulation each give the one-at-a-time rate.  Each request carries its initial fields
+    (built before the clock starts); upload, initialisation, the steps and the download of the
+    result fields are timed."""
     from paper_1705_10045_amd import inputs as I
     from paper_1705_10045_amd import lbm
     from paper_1705_10045_amd import serve
@@ -253,7 +345,10 @@ def serving_bench(count=48, steps_range=(100, 1000), budget_gib=4.0, max_slots=6
                 "completed": r["completed"], "failed": r["failed"],
                 "failed_ids": [reqs[i]["id"] for i, st in enumerate(r["status"]) if st not in (0, None)],
                 "peak_in_flight": r["peak_in_flight"], "replays": r["replays"]}
-    return {"requests": count, "edges": sorted(set(r["edge"] for r in reqs)),
+    return {"requests": count,
+            "stream": "requests 0..%d of the %d-request serving stream, listed step counts" %
+                      (count - 1, SERVING_STREAM),
+            "edges": sorted(set(r["edge"] for r in reqs)),
             "steps_range": list(steps_range), "node_updates": int(work.sum()),
             "hbm_budget_gib": budget_gib, "max_slots": max_slots,
             "steps_per_replay": steps_per_run,
@@ -320,22 +415,22 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="droplet128")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="1 GiB device copies only (calibration of rocprofv3 byte counters)")
     ap.add_argument("--ceiling", action="store_true",
-                    help="time a plain device copy of the step's state at 128^3 and 256^3")
+                    help="time plain device copies of the step's state at 128^3, 256^3 and 512^3")
     ap.add_argument("--sweep", action="store_true",
                     help="time every tile variant x z-chunk of the step kernel (tuning)")
     ap.add_argument("--serving", action="store_true",
                     help="only the serving measurement (burst, Poisson stream, one at a time)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving measurement in the default line")
-    ap.add_argument("--serving-requests", type=int, default=48)
+    ap.add_argument("--serving-requests", type=int, default=SERVING_DEFAULT_COUNT)
     ap.add_argument("--serving-full", action="store_true",
-                    help="with --serving: the full request stream (512 requests, 500..5000 steps, "
-                         "64 GiB pool) instead of the short default")
+                    help="with --serving: the whole request stream (512 requests) instead of the "
+                         "benchmark line's first %d" % SERVING_DEFAULT_COUNT)
     ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--chunk", type=int, default=0)
     args = ap.parse_args()
@@ -358,10 +453,7 @@ def main():
         lib_build.build()
 
     if args.serving:
-        if args.serving_full:   # the serving configuration as listed: 512 requests, 500..5000 steps
-            rep = serving_bench(count=512, steps_range=(500, 5000), budget_gib=64.0)
-        else:
-            rep = serving_bench(count=args.serving_requests)
+        rep = serving_bench(count=SERVING_STREAM if args.serving_full else args.serving_requests)
         print(json.dumps({"metric": "serving time-to-result (p50/p99) and aggregate MLUPS",
                           "serving": rep}), flush=True)
         return
@@ -419,7 +511,7 @@ def main():
         out["serving"] = serving_bench(count=args.serving_requests)
     if not args.no_cpu_baseline:
         launch = (args.variant or 0, args.chunk) if (args.variant is not None or args.chunk) else None
-        out["cpu_baseline"] = cpu_baseline(case, storage, launch)
+        out["cpu_baseline"] = cpu_baseline(args.workload, case, storage, launch)
     print(json.dumps(out), flush=True)
 
 

@@ -52,6 +52,13 @@ enum {
     LBM_COLLISION_MRT = 1   /* moments of N_k - Neq(rho, u) relax at their own rates         */
 };
 
+/* Equation of state (lbm_params.eos).  Section 3 uses the reduced van der Waals EOS and names
+ * tabulated equations of state of real fluids as the alternative. */
+enum {
+    LBM_EOS_VDW = 0,    /* p = p_c p~(rho/rho_c, T/T_c), reduced van der Waals                */
+    LBM_EOS_TABLE = 1   /* p~ interpolated in a caller's table (see lbm_params.eos_p)         */
+};
+
 /* Physical terms (the ablations of sections 4-6). */
 enum {
     LBM_WORK = 1u,         /* pressure work -p div u*                                      */
@@ -101,6 +108,23 @@ typedef struct {
      * LBM_COLLISION_BGK. */
     int collision;
     double s_e, s_eps, s_q, s_m;
+    /* Equation of state.  LBM_EOS_VDW (0, default): the reduced van der Waals EOS.
+     * LBM_EOS_TABLE: the reduced pressure p~ = p/p_c is given by the caller on a uniform grid,
+     * eos_p[j * eos_nrho + i] at rho~_i = eos_rho_min + i (eos_rho_max - eos_rho_min)/(eos_nrho - 1)
+     * and T~_j = eos_T_min + j (eos_T_max - eos_T_min)/(eos_nT - 1) (rho~ = rho/rho_c,
+     * T~ = T/T_c), and interpolated cubically in rho~ (Lagrange, the four grid densities around
+     * the point, the stencil shifted inward next to the ends) and linearly in T~ between the two
+     * rows around the point.  A node outside the grid has left the EOS domain (LBM_EUNSTABLE).
+     * eos_coex[2j], eos_coex[2j + 1] are the reduced coexistence densities rho_1 <= rho_2 of row
+     * j, the band of the latent heat (section 5), linear in T~ between rows; the latent source
+     * acts over the table's whole temperature range (rho_1 = rho_2 leaves a row without band).
+     * Both host arrays are read by lbm_init, which keeps its own device copy; eos_nrho >= 4,
+     * eos_nT >= 2, at most 2^26 points.  Not accepted by the serving pool. */
+    int eos;
+    const double* eos_p;
+    const double* eos_coex;
+    int eos_nrho, eos_nT;
+    double eos_rho_min, eos_rho_max, eos_T_min, eos_T_max;
 } lbm_params;
 
 typedef struct lbm_sim lbm_sim;
@@ -238,6 +262,14 @@ lbm_status lbm_pool_submit(lbm_pool* pool, const lbm_params* params, const doubl
 /* Advance every active request by up to steps_per_run steps; synchronises and refreshes the
  * completion state. */
 lbm_status lbm_pool_run(lbm_pool* pool);
+
+/* The same replay without waiting for it: waits for the replay a previous call left in flight
+ * (if any), refreshes the completion state from it, then enqueues the next replay of every
+ * active request and returns.  Submissions and collections made while a replay is in flight
+ * run on a second stream and overlap it (a request admitted then joins the next replay);
+ * lbm_pool_poll reports the state as of the last replay waited for.  A call with no active
+ * request only waits and refreshes.  lbm_pool_run waits for the replay it starts. */
+lbm_status lbm_pool_run_async(lbm_pool* pool);
 
 /* Completion of a ticket: *done = 1 when all its steps have run; *result = LBM_OK or
  * LBM_EUNSTABLE for a request that left the EOS domain (retired early, others unaffected). */

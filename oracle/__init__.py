@@ -26,6 +26,9 @@ ALL_TERMS = WORK | CONDUCTION | LATENT | PSEUDOFORCE
 BGK = 0
 MRT = 1
 
+EOS_VDW = 0
+EOS_TABLE = 1
+
 WALL_T_BOTTOM = 1
 WALL_T_TOP = 2
 
@@ -47,6 +50,11 @@ class _Params(ctypes.Structure):
         ("collision", ctypes.c_int),
         ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double), ("s_q", ctypes.c_double),
         ("s_m", ctypes.c_double),
+        ("eos", ctypes.c_int),
+        ("eos_p", ctypes.POINTER(ctypes.c_double)), ("eos_coex", ctypes.POINTER(ctypes.c_double)),
+        ("eos_nrho", ctypes.c_int), ("eos_nT", ctypes.c_int),
+        ("eos_rho_min", ctypes.c_double), ("eos_rho_max", ctypes.c_double),
+        ("eos_T_min", ctypes.c_double), ("eos_T_max", ctypes.c_double),
     ]
 
 
@@ -62,6 +70,9 @@ def _lib():
         lib = ctypes.CDLL(_build.LIB)
         lib.orc_vdw_reduced.restype = ctypes.c_double
         lib.orc_vdw_reduced.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.orc_table_reduced.restype = ctypes.c_double
+        lib.orc_table_reduced.argtypes = [ctypes.POINTER(_Params), ctypes.c_double,
+                                          ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
         lib.orc_maxwell.argtypes = [ctypes.c_double, _D, _D, _D]
         lib.orc_lattice.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D, _D, _D]
         lib.orc_equilibrium.argtypes = [ctypes.c_int, ctypes.c_double, _D, _D]
@@ -123,6 +134,34 @@ def mrt_basis(Q):
 
 def vdw_reduced(rr, Tr):
     return _lib().orc_vdw_reduced(float(rr), float(Tr))
+
+
+def _table_fields(p, table):
+    """Set the tabulated-EOS fields of a _Params from a dict with keys p (nT x nrho reduced
+    pressures), coex (nT x 2 reduced band limits), rho_range and T_range; returns the arrays,
+    which must stay alive while p is used."""
+    tp = np.ascontiguousarray(table["p"], dtype=np.float64)
+    tc = np.ascontiguousarray(table["coex"], dtype=np.float64)
+    if tp.ndim != 2 or tc.shape != (tp.shape[0], 2):
+        raise ValueError("table p must be (nT, nrho) and coex (nT, 2)")
+    p.eos = EOS_TABLE
+    p.eos_p = _ptr(tp)
+    p.eos_coex = _ptr(tc)
+    p.eos_nT, p.eos_nrho = tp.shape
+    p.eos_rho_min, p.eos_rho_max = (float(v) for v in table["rho_range"])
+    p.eos_T_min, p.eos_T_max = (float(v) for v in table["T_range"])
+    return tp, tc
+
+
+def table_reduced(table, rr, Tr):
+    """Reduced pressure of a tabulated EOS (dict as for Sim's params["eos_table"]) at (rr, Tr),
+    or None outside its grid."""
+    p = _Params()
+    keep = _table_fields(p, table)
+    inside = ctypes.c_int()
+    v = _lib().orc_table_reduced(ctypes.byref(p), float(rr), float(Tr), ctypes.byref(inside))
+    del keep
+    return v if inside.value else None
 
 
 def maxwell(Tr):
@@ -228,10 +267,14 @@ class Sim:
         p.collision = int(params.get("collision", _MRT_DEFAULTS["collision"]))
         for k in ("s_e", "s_eps", "s_q", "s_m"):
             setattr(p, k, float(params.get(k, _MRT_DEFAULTS[k])))
+        # optional tabulated equation of state: params["eos_table"] = dict(p=(nT, nrho) reduced
+        # pressures, coex=(nT, 2) reduced band limits, rho_range=(min, max), T_range=(min, max))
+        keep = _table_fields(p, params["eos_table"]) if params.get("eos_table") else None
         self.Q, self.shape = Q, rho0.shape
         self._p = p
         st = ctypes.c_int()
         h = _lib().orc_create(ctypes.byref(p), _ptr(rho0), _ptr(u0), _ptr(T0), ctypes.byref(st))
+        del keep   # the oracle copied the table
         if not h:
             raise ValueError("oracle rejected the parameters or initial fields (status %d)"
                              % st.value)

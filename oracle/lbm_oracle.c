@@ -35,7 +35,10 @@
  *   - g^eq and dg(2) use u from eq:hydro and the same du as the N_k;
  *   - the latent source uses rho_liq*Q as one constant (rhoQ) and is active
  *     where 0.4 <= T~ < 0.999 and rho_1(T) < rho < rho_2(T) strictly, with
- *     rho_1, rho_2 the Maxwell coexistence densities at the EOS temperature.
+ *     rho_1, rho_2 the Maxwell coexistence densities at the EOS temperature;
+ *   - a tabulated EOS (section 3 allows them for real fluids) is interpolated
+ *     cubically in rho~ and linearly in T~ on its uniform grid, and carries its
+ *     own coexistence band for the latent source.
  *
  * Collision of N_k: BGK (eq:lbe) or, as section 2 also allows, multiple relaxation times on an
  * orthogonal moment basis (MRT), with the EDM increment added in either case.
@@ -207,6 +210,64 @@ int orc_mrt_basis(int Q, double* M, double* norm2, int* group)
 double orc_vdw_reduced(double rr, double Tr)
 {
     return 8.0 * rr * Tr / (3.0 - rr) - 3.0 * rr * rr;
+}
+
+/* ---------------------------------------------------------------------------
+ * Tabulated equation of state (section 3: tabulated EOS of real fluids).
+ * Cubic Lagrange interpolation in rho~ on the four grid points around the point,
+ * linear interpolation in T~ between the two rows around it.
+ * ------------------------------------------------------------------------- */
+
+/* Value at offset t (in grid steps from node 0) of the cubic through f[0..3] at nodes 0..3. */
+static double lagrange4(const double* f, double t)
+{
+    const double l0 = -(t - 1.0) * (t - 2.0) * (t - 3.0) / 6.0;
+    const double l1 = t * (t - 2.0) * (t - 3.0) / 2.0;
+    const double l2 = -t * (t - 1.0) * (t - 3.0) / 2.0;
+    const double l3 = t * (t - 1.0) * (t - 2.0) / 6.0;
+    return l0 * f[0] + l1 * f[1] + l2 * f[2] + l3 * f[3];
+}
+
+/* Grid row j and weight u of the second row for reduced temperature Tr; 0 outside. */
+static int table_row(const orc_params* p, double Tr, int* j, double* u)
+{
+    if (!(Tr >= p->eos_T_min && Tr <= p->eos_T_max)) return 0;
+    const double dT = (p->eos_T_max - p->eos_T_min) / (p->eos_nT - 1);
+    int r = (int)floor((Tr - p->eos_T_min) / dT);
+    if (r > p->eos_nT - 2) r = p->eos_nT - 2;
+    if (r < 0) r = 0;
+    *j = r;
+    *u = (Tr - (p->eos_T_min + r * dT)) / dT;
+    return 1;
+}
+
+double orc_table_reduced(const orc_params* p, double rr, double Tr, int* inside)
+{
+    int j;
+    double u;
+    *inside = 0;
+    if (!(rr >= p->eos_rho_min && rr <= p->eos_rho_max) || !table_row(p, Tr, &j, &u)) return 0.0;
+    const double dr = (p->eos_rho_max - p->eos_rho_min) / (p->eos_nrho - 1);
+    /* stencil i0 .. i0+3 with the point between i0+1 and i0+2 where the grid allows */
+    int i0 = (int)floor((rr - p->eos_rho_min) / dr) - 1;
+    if (i0 < 0) i0 = 0;
+    if (i0 > p->eos_nrho - 4) i0 = p->eos_nrho - 4;
+    const double t = (rr - (p->eos_rho_min + i0 * dr)) / dr;
+    const double lo = lagrange4(p->eos_p + (long)j * p->eos_nrho + i0, t);
+    const double hi = lagrange4(p->eos_p + (long)(j + 1) * p->eos_nrho + i0, t);
+    *inside = 1;
+    return (1.0 - u) * lo + u * hi;
+}
+
+/* Coexistence band (reduced rho_1, rho_2) of the tabulated EOS at Tr; 0 outside the table. */
+static int table_band(const orc_params* p, double Tr, double* r1, double* r2)
+{
+    int j;
+    double u;
+    if (!table_row(p, Tr, &j, &u)) return 0;
+    *r1 = (1.0 - u) * p->eos_coex[2 * j] + u * p->eos_coex[2 * j + 2];
+    *r2 = (1.0 - u) * p->eos_coex[2 * j + 1] + u * p->eos_coex[2 * j + 3];
+    return 1;
 }
 
 /* Chemical potential of the reduced vdW fluid up to a T-dependent constant,
@@ -474,7 +535,8 @@ int orc_conduction_walls(int nx, int ny, int nz, double c_v, double chi, const d
  * ------------------------------------------------------------------------- */
 
 struct orc_sim {
-    orc_params p;
+    orc_params p;                   /* eos_p, eos_coex point at the copies below */
+    double *eos_p, *eos_coex;
     lattice L;
     long n;
     long long step;
@@ -515,6 +577,16 @@ static int valid_params(const orc_params* p)
     for (int a = 0; a < 3; ++a)
         if (!isfinite(p->gravity[a])) return 0;
     if (p->collision != ORC_BGK && p->collision != ORC_MRT) return 0;
+    if (p->eos != ORC_EOS_VDW && p->eos != ORC_EOS_TABLE) return 0;
+    if (p->eos == ORC_EOS_TABLE) {
+        if (!p->eos_p || !p->eos_coex || p->eos_nrho < 4 || p->eos_nT < 2) return 0;
+        if (!(p->eos_rho_max > p->eos_rho_min && p->eos_rho_min >= 0.0)) return 0;
+        if (!(p->eos_T_max > p->eos_T_min && p->eos_T_min > 0.0)) return 0;
+        for (long i = 0; i < (long)p->eos_nrho * p->eos_nT; ++i)
+            if (!isfinite(p->eos_p[i])) return 0;
+        for (long j = 0; j < p->eos_nT; ++j)
+            if (!(p->eos_coex[2 * j] <= p->eos_coex[2 * j + 1])) return 0;
+    }
     if (p->collision == ORC_MRT) {
         if (!(p->Q == 9 || p->Q == 19)) return 0;
         const double r[4] = {p->s_e, p->s_eps, p->s_q, p->s_m};
@@ -531,6 +603,18 @@ orc_sim* orc_create(const orc_params* p, const double* rho0, const double* u0, c
     if (!p || !valid_params(p) || !rho0 || !u0 || !T0) return NULL;
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
     s->p = *p;
+    if (p->eos == ORC_EOS_TABLE) {
+        const size_t np = (size_t)p->eos_nrho * p->eos_nT;
+        s->eos_p = (double*)malloc(sizeof(double) * np);
+        s->eos_coex = (double*)malloc(sizeof(double) * 2 * p->eos_nT);
+        memcpy(s->eos_p, p->eos_p, sizeof(double) * np);
+        memcpy(s->eos_coex, p->eos_coex, sizeof(double) * 2 * p->eos_nT);
+        s->p.eos_p = s->eos_p;
+        s->p.eos_coex = s->eos_coex;
+    } else {
+        s->p.eos_p = NULL;
+        s->p.eos_coex = NULL;
+    }
     make_lattice(p->Q, &s->L);
     const long n = (long)p->nx * p->ny * p->nz;
     const int Q = p->Q;
@@ -561,6 +645,8 @@ void orc_free(orc_sim* s)
     double* fields[] = {s->N, s->g, s->Np, s->gp, s->rho, s->j, s->u, s->E, s->T, s->pr, s->Phi,
                         s->F, s->du, s->us, s->divu, s->work, s->cond, s->latent, s->dE};
     for (size_t i = 0; i < sizeof(fields) / sizeof(fields[0]); ++i) free(fields[i]);
+    free(s->eos_p);
+    free(s->eos_coex);
     free(s);
 }
 
@@ -603,10 +689,12 @@ static int pass_eos(orc_sim* s)
     for (long i = 0; i < n; ++i) {
         double rr = s->rho[i] / s->p.rho_c;
         double Tr = eos_temperature(s, i) / s->p.T_c;
-        double p = s->p.p_c * orc_vdw_reduced(rr, Tr);
+        int inside = 1;
+        double p = s->p.eos == ORC_EOS_TABLE ? s->p.p_c * orc_table_reduced(&s->p, rr, Tr, &inside)
+                                             : s->p.p_c * orc_vdw_reduced(rr, Tr);
         double minusU = s->rho[i] * THETA - p;
         s->pr[i] = p;
-        if (!(minusU > 0.0) || !(rr < 3.0) || !isfinite(s->E[i]) || !(s->rho[i] > 0.0)) {
+        if (!inside || !(minusU > 0.0) || !(rr < 3.0) || !isfinite(s->E[i]) || !(s->rho[i] > 0.0)) {
             ok = 0;
             s->Phi[i] = 0.0;
         } else {
@@ -656,9 +744,13 @@ static void pass_energy_source(orc_sim* s)
         s->latent[i] = 0.0;
         if (p->flags & ORC_LATENT) {
             double Tr = eos_temperature(s, i) / p->T_c;
-            if (Tr >= LATENT_TMIN && Tr < LATENT_TMAX) {
-                double rv, rl;
-                orc_maxwell(Tr, &rv, &rl, NULL);
+            double rv, rl;
+            int band = 0;
+            if (p->eos == ORC_EOS_TABLE)
+                band = table_band(p, Tr, &rv, &rl);
+            else if (Tr >= LATENT_TMIN && Tr < LATENT_TMAX)
+                band = orc_maxwell(Tr, &rv, &rl, NULL) == ORC_OK;
+            if (band) {
                 double r1 = rv * p->rho_c, r2 = rl * p->rho_c;
                 if (s->rho[i] > r1 && s->rho[i] < r2)
                     s->latent[i] = -p->rhoQ / (r2 - r1) * s->rho[i] * s->divu[i];

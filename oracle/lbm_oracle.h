@@ -33,6 +33,9 @@ extern "C" {
 #define ORC_BGK 0           /* collision of N_k: one relaxation time tau (section 2)   */
 #define ORC_MRT 1           /* several relaxation times on an orthogonal moment basis */
 
+#define ORC_EOS_VDW   0     /* reduced van der Waals equation of state (section 3)     */
+#define ORC_EOS_TABLE 1     /* reduced pressure interpolated in a table (section 3)    */
+
 #define ORC_OK         0
 #define ORC_EINVAL    -1
 #define ORC_EUNSTABLE -3
@@ -64,6 +67,22 @@ typedef struct {
      * populations g_k keep the single relaxation time tau_E of eq:gk. */
     int collision;
     double s_e, s_eps, s_q, s_m;
+    /* Equation of state.  ORC_EOS_VDW: p = p_c p~(rho/rho_c, T/T_c) with the reduced van der
+     * Waals p~ of section 3.  ORC_EOS_TABLE: section 3 allows tabulated equations of state of
+     * real fluids; p~ is then interpolated in eos_p, given on the uniform grid
+     * rho~_i = eos_rho_min + i (eos_rho_max - eos_rho_min)/(eos_nrho - 1),
+     * T~_j = eos_T_min + j (eos_T_max - eos_T_min)/(eos_nT - 1), eos_p[j*eos_nrho + i]:
+     * cubic Lagrange interpolation in rho~ through the four grid densities around the point
+     * (the stencil shifted inward at the ends), linear in T~ between the two grid rows around
+     * it.  A node outside the grid has left the EOS domain.  The coexistence band of the latent
+     * heat (section 5) is eos_coex[2j], eos_coex[2j+1] (reduced rho_1 <= rho_2) at row j,
+     * linear in T~ between rows; it acts over the table's whole temperature range.  Both arrays
+     * are read at orc_create and copied. */
+    int eos;
+    const double* eos_p;
+    const double* eos_coex;
+    int eos_nrho, eos_nT;
+    double eos_rho_min, eos_rho_max, eos_T_min, eos_T_max;
 } orc_params;
 
 /* Lattice tables: c[Q*3], w[Q], G[Q] (G[0] = 0), alpha.  Returns D or ORC_EINVAL. */
@@ -76,6 +95,10 @@ int orc_mrt_basis(int Q, double* M, double* norm2, int* group);
 
 /* Reduced van der Waals pressure p~(rho~, T~) (section 3). */
 double orc_vdw_reduced(double rr, double Tr);
+
+/* Reduced pressure of the tabulated equation of state of p (ORC_EOS_TABLE) at (rr, Tr);
+ * *inside = 0 (and 0 returned) outside the table's grid. */
+double orc_table_reduced(const orc_params* p, double rr, double Tr, int* inside);
 
 /* Maxwell equal-chemical-potential coexistence at reduced temperature Tr in (0,1):
  * reduced vapour density, liquid density and saturation pressure. */

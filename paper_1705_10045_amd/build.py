@@ -1,4 +1,5 @@
-"""Build the HIP library liblbm_mi355x.so for gfx950 in-tree (paper_1705_10045_amd/_build/).
+"""Build the HIP library liblbm_mi355x.so for gfx950 in-tree (paper_1705_10045_amd/_build/), and
+the benchmark's bandwidth-ceiling probe libceiling.so beside it.
 
 Every source is compiled by hipcc for gfx950 only, with packed FP32 instructions disabled;
 objects are compiled in parallel and linked into one shared library exposing the C ABI of
@@ -14,6 +15,9 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "liblbm_mi355x.so")
 SOURCES = ["api.hip", "kernels.hip", "serve.hip", "noalloc.hip"]
+# the bandwidth-ceiling probe of the benchmark, a library of its own (not part of the ABI)
+PROBE_SOURCES = ["ceiling.hip"]
+PROBE_LIB = os.path.join(OUT_DIR, "libceiling.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
@@ -36,16 +40,21 @@ def _compile(src, verbose):
     return obj
 
 
-def build(verbose=False):
-    os.makedirs(OUT_DIR, exist_ok=True)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = LIB + ".tmp%d" % os.getpid()
+def _link(objs, out, verbose):
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose=False):
+    os.makedirs(OUT_DIR, exist_ok=True)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES) + len(PROBE_SOURCES)) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES + PROBE_SOURCES))
+    _link(objs[:len(SOURCES)], LIB, verbose)
+    _link(objs[len(SOURCES):], PROBE_LIB, verbose)
     return LIB
 
 

@@ -129,6 +129,30 @@ double dp_drho(double rho, double T, const Phys& ph)
     return ph.p_c * ph.inv_rho_c * (24.0 * tr / (a * a) - 6.0 * rr);
 }
 
+// Pressure in lattice units of the simulation's EOS (the tabulated one from its host table);
+// `inside` false outside a table's grid.
+double host_pressure(double rho, double T, const Phys& ph, const double* table, bool& inside)
+{
+    inside = true;
+    if (ph.eos == 0) return vdw_pressure(rho, T, ph);
+    return ph.p_c * table_pressure(rho * ph.inv_rho_c, T * ph.inv_T_c, ph, table, inside);
+}
+
+// dp/drho at fixed T of the simulation's EOS: analytic for van der Waals, a central
+// difference of the interpolant for a table (one-sided next to the grid's ends).
+double host_dp_drho(double rho, double T, const Phys& ph, const double* table)
+{
+    if (ph.eos == 0) return dp_drho(rho, T, ph);
+    const double h = 1e-6 * ph.rho_c;
+    bool in_lo, in_hi;
+    double lo_r = rho - h, hi_r = rho + h;
+    double plo = host_pressure(lo_r, T, ph, table, in_lo);
+    double phi = host_pressure(hi_r, T, ph, table, in_hi);
+    if (!in_lo) { lo_r = rho; plo = host_pressure(rho, T, ph, table, in_lo); }
+    if (!in_hi) { hi_r = rho; phi = host_pressure(rho, T, ph, table, in_hi); }
+    return (phi - plo) / (hi_r - lo_r);
+}
+
 }  // namespace
 
 bool host_band_limits(double Tr, double& rv, double& rl)
@@ -175,6 +199,15 @@ Phys make_phys(const lbm_params& p)
     ph.mrt_deps = mrt ? p.s_eps - ph.omega : 0.0;
     ph.mrt_dq = mrt ? p.s_q - ph.omega : 0.0;
     ph.mrt_dm = mrt ? p.s_m - ph.omega : 0.0;
+    ph.eos = p.eos == LBM_EOS_TABLE ? 1 : 0;
+    ph.tab_nrho = ph.eos ? p.eos_nrho : 0;
+    ph.tab_nT = ph.eos ? p.eos_nT : 0;
+    ph.tab_rho_min = p.eos_rho_min;
+    ph.tab_rho_max = p.eos_rho_max;
+    ph.tab_T_min = p.eos_T_min;
+    ph.tab_T_max = p.eos_T_max;
+    ph.tab_drho = ph.eos ? (p.eos_rho_max - p.eos_rho_min) / (p.eos_nrho - 1) : 0.0;
+    ph.tab_dT = ph.eos ? (p.eos_T_max - p.eos_T_min) / (p.eos_nT - 1) : 0.0;
     return ph;
 }
 
@@ -236,6 +269,29 @@ lbm_status validate_params(const lbm_params* p)
         for (int i = 0; i < 4; ++i)
             if (!(r[i] > 0.0 && r[i] < 2.0)) { set_error("MRT rates must lie in (0, 2)"); return LBM_EINVAL; }
     }
+    if (p->eos != LBM_EOS_VDW && p->eos != LBM_EOS_TABLE) {
+        set_error("eos must be LBM_EOS_VDW (0) or LBM_EOS_TABLE (1), got %d", p->eos);
+        return LBM_EINVAL;
+    }
+    if (p->eos == LBM_EOS_TABLE) {
+        if (!p->eos_p || !p->eos_coex || p->eos_nrho < 4 || p->eos_nT < 2 ||
+            (long long)p->eos_nrho * p->eos_nT > (1LL << 26)) {
+            set_error("a tabulated EOS needs eos_p and eos_coex, eos_nrho >= 4, eos_nT >= 2 and at most 2^26 points");
+            return LBM_EINVAL;
+        }
+        if (!(p->eos_rho_max > p->eos_rho_min && p->eos_rho_min >= 0.0 && std::isfinite(p->eos_rho_max)) ||
+            !(p->eos_T_max > p->eos_T_min && p->eos_T_min > 0.0 && std::isfinite(p->eos_T_max))) {
+            set_error("a tabulated EOS needs 0 <= eos_rho_min < eos_rho_max and 0 < eos_T_min < eos_T_max");
+            return LBM_EINVAL;
+        }
+        for (long long i = 0; i < (long long)p->eos_nrho * p->eos_nT; ++i)
+            if (!std::isfinite(p->eos_p[i])) { set_error("EOS table value %lld is not finite", i); return LBM_EINVAL; }
+        for (int j = 0; j < p->eos_nT; ++j)
+            if (!(p->eos_coex[2 * j] <= p->eos_coex[2 * j + 1]) || !std::isfinite(p->eos_coex[2 * j + 1])) {
+                set_error("EOS coexistence row %d needs finite rho_1 <= rho_2", j);
+                return LBM_EINVAL;
+            }
+    }
     // the step addresses nodes within one population plane with 32-bit byte offsets
     const long long n = (long long)p->nx * p->ny * p->nz;
     if ((unsigned long long)padded_plane(n) * (unsigned long long)p->storage_bytes >= (1ull << 32)) {
@@ -263,13 +319,20 @@ lbm_status validate_fields(const lbm_params& p, const double* rho0, const double
             return LBM_EINVAL;
         }
         const double Te = (p.flags & LBM_BAROTROPIC) ? p.T0_baro : T;
-        if (!(r * kTheta - vdw_pressure(r, Te, ph) > 0)) {
+        bool inside;
+        const double pr = host_pressure(r, Te, ph, p.eos_p, inside);
+        if (!inside) {
+            set_error("node %lld: (rho, T) = (%g, %g) outside the EOS table", i, r, Te);
+            return LBM_EINVAL;
+        }
+        if (!(r * kTheta - pr > 0)) {
             set_error("node %lld: Phi^2 = rho theta - p <= 0 (section 3)", i);
             return LBM_EINVAL;
         }
-        if (dp_drho(r, Te, ph) > bound) {
-            set_error("node %lld: (dp/drho)_T = %g exceeds the stability bound %g (section 3)", i,
-                      dp_drho(r, Te, ph), bound);
+        const double dpdr = host_dp_drho(r, Te, ph, p.eos_p);
+        if (dpdr > bound) {
+            set_error("node %lld: (dp/drho)_T = %g exceeds the stability bound %g (section 3)", i, dpdr,
+                      bound);
             return LBM_EINVAL;
         }
     }
@@ -364,7 +427,10 @@ const char* lbm_last_error(void) { return g_last_error; }
 size_t lbm_footprint_bytes(const lbm_params* p)
 {
     if (!p) return 0;
-    return 2 * state_bytes(*p) + sizeof(double) * 2 * kMaxwellPoints + 64;
+    size_t tables = sizeof(double) * 2 * kMaxwellPoints + 64;
+    if (p->eos == LBM_EOS_TABLE && p->eos_nrho > 0 && p->eos_nT > 0)
+        tables += sizeof(double) * ((size_t)p->eos_nrho * p->eos_nT + 2 * (size_t)p->eos_nT);
+    return 2 * state_bytes(*p) + tables;
 }
 
 int lbm_lattice_info(int Q, int* c, double* w, double* G, double* alpha)
@@ -453,6 +519,20 @@ lbm_status lbm_init(const lbm_params* params, const double* rho0, const double* 
     if (e != hipSuccess) { lbm_status r = hip_fail(e, "clear state"); lbm_free(s); return r; }
     st = upload_table(s);
     if (st != LBM_OK) { lbm_free(s); return st; }
+    if (s->phys.eos) {
+        // the simulation keeps its own device copy of the caller's tables
+        const size_t np = (size_t)params->eos_nrho * params->eos_nT, nc = 2 * (size_t)params->eos_nT;
+        e = hipMalloc((void**)&s->d_eos_p, sizeof(double) * np);
+        if (e == hipSuccess) e = hipMalloc((void**)&s->d_eos_coex, sizeof(double) * nc);
+        if (e == hipSuccess) e = hipMemcpy(s->d_eos_p, params->eos_p, sizeof(double) * np, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(s->d_eos_coex, params->eos_coex, sizeof(double) * nc, hipMemcpyHostToDevice);
+        if (e != hipSuccess) { lbm_status r = hip_fail(e, "EOS table upload"); lbm_free(s); return r; }
+    }
+    s->aux.eos_p = s->d_eos_p;
+    s->aux.eos_coex = s->d_eos_coex;
+    // the caller's table pointers are not kept
+    s->p.eos_p = nullptr;
+    s->p.eos_coex = nullptr;
 
     double* d_fields = nullptr;
     e = hipMalloc((void**)&d_fields, sizeof(double) * 5 * s->n);
@@ -536,7 +616,8 @@ lbm_status lbm_moments_device(lbm_sim* s, double* rho, double* u_star, double* E
     lbm_status st = ensure_scratch(s);
     if (st != LBM_OK) return st;
     hipError_t e = launch_moments(s->p.lattice, s->p.storage_bytes, s->buf[s->cur], s->d_scratch, s->p.nx,
-                                  s->p.ny, s->p.nz, s->plane, s->phys, s->d_err, rho, u_star, E, T, s->stream);
+                                  s->p.ny, s->p.nz, s->plane, s->phys, s->aux.eos_p, s->d_err, rho, u_star, E,
+                                  T, s->stream);
     if (e != hipSuccess) return hip_fail(e, "moments launch");
     return LBM_OK;
 }
@@ -552,8 +633,8 @@ lbm_status lbm_moments(lbm_sim* s, double* rho, double* u_star, double* E, doubl
     double* scr = s->d_scratch;
     double* d_us = scr + 7 * n;
     hipError_t e = launch_moments(s->p.lattice, s->p.storage_bytes, s->buf[s->cur], scr, s->p.nx, s->p.ny,
-                                  s->p.nz, s->plane, s->phys, s->d_err, nullptr, u_star ? d_us : nullptr,
-                                  nullptr, nullptr, s->stream);
+                                  s->p.nz, s->plane, s->phys, s->aux.eos_p, s->d_err, nullptr,
+                                  u_star ? d_us : nullptr, nullptr, nullptr, s->stream);
     if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, scr, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess && u_star) e = hipMemcpyAsync(u_star, d_us, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess && E) e = hipMemcpyAsync(E, scr + 4 * n, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream);
@@ -640,6 +721,8 @@ lbm_status lbm_free(lbm_sim* s)
     if (s->d_partials) (void)hipFree(s->d_partials);
     if (s->d_table) (void)hipFree(s->d_table);
     if (s->d_scratch) (void)hipFree(s->d_scratch);
+    if (s->d_eos_p) (void)hipFree(s->d_eos_p);
+    if (s->d_eos_coex) (void)hipFree(s->d_eos_coex);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
     return LBM_OK;

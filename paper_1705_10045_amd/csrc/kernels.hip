@@ -59,7 +59,8 @@ __global__ void k_init(S* __restrict__ buf, const double* __restrict__ rho0,
 // Moments of the current state in FP64: scratch = [rho | jx | jy | jz | E | T | Phi].
 template <int Q, class S>
 __global__ void k_moments_a(const S* __restrict__ buf, double* __restrict__ scr, int nx, int ny,
-                            int nz, long long plane, Phys ph, int* err)
+                            int nz, long long plane, Phys ph, const double* __restrict__ eos_p,
+                            int* err)
 {
     using L = Lattice<Q>;
     const long long n = (long long)nx * ny * nz;
@@ -85,8 +86,11 @@ __global__ void k_moments_a(const S* __restrict__ buf, double* __restrict__ scr,
     }
     const double T = E / (rho * ph.c_v);
     const double Te = (ph.flags & kBaro) ? ph.T0_baro : T;
-    double phi2 = rho * kTheta - vdw_pressure(rho, Te, ph);
-    if (!(phi2 > 0.0) || !(rho * ph.inv_rho_c < 3.0) || !(rho > 0.0) || !(E == E)) {
+    bool inside = true;
+    const double p = ph.eos ? ph.p_c * table_pressure(rho * ph.inv_rho_c, Te * ph.inv_T_c, ph, eos_p, inside)
+                            : vdw_pressure(rho, Te, ph);
+    double phi2 = rho * kTheta - p;
+    if (!inside || !(phi2 > 0.0) || !(rho * ph.inv_rho_c < 3.0) || !(rho > 0.0) || !(E == E)) {
         atomicOr(err, 1);
         phi2 = 0.0;
     }
@@ -195,40 +199,45 @@ inline unsigned blocks_for(long long n, int threads)
     return (unsigned)((n + threads - 1) / threads);
 }
 
-// Buffer-resource addressing needs every byte offset of the two population sets in 32 bits.
+// One buffer resource per buffer needs every byte offset of the two population sets in 32 bits.
 inline bool fits_buffer(const StepGeom& g, int Q, int storage_bytes)
 {
     return (unsigned long long)g.plane * 2ull * Q * storage_bytes < (1ull << 32);
 }
 
-// The periodic instantiation, or the one with walls and body force when the parameters ask
-// for them.
-template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool STASH, bool BUF,
+
+// The periodic instantiation, the one with walls and body force when the parameters ask for
+// them, or the one that also carries the tabulated equation of state.
+template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool STASH, int ADDR,
           int NMODE>
 hipError_t launch_one(const void* src, void* dst, const StepGeom& g, const Phys& ph,
                       const StepAux& aux, hipStream_t st)
 {
     const unsigned nblk = (unsigned)(g.ntx * g.nty * g.nchunks);
     const bool ext = ph.walls || ph.g[0] != 0.0 || ph.g[1] != 0.0 || ph.g[2] != 0.0;
-    if (ext)
-        hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, STASH, true>),
+    if (ph.eos != 0)
+        hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, NTH, PIPE, ADDR, NMODE, STASH, kExtTable>),
+                           dim3(nblk), dim3(NTH), 0, st, (const S*)src, (S*)dst, g, ph, aux);
+    else if (ext)
+        hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, NTH, PIPE, ADDR, NMODE, STASH, kExtWalls>),
                            dim3(nblk), dim3(NTH), 0, st, (const S*)src, (S*)dst, g, ph, aux);
     else
-        hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, STASH, false>),
+        hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, NTH, PIPE, ADDR, NMODE, STASH, kExtNone>),
                            dim3(nblk), dim3(NTH), 0, st, (const S*)src, (S*)dst, g, ph, aux);
     return hipGetLastError();
 }
 
-// Picks the instantiation for the run-time facts: buffer addressing if the state allows it,
-// the tau = 1 collision (no re-read of N_k) when 1/tau is exactly 1 with BGK, and the MRT
-// collision (which re-reads N_k, with the load order of tau != 1) when asked for.  Where a variant asks
-// for the LDS stash, it is used where it measured faster on MI355X and fits the registers:
-//   - FP32 with buffer addressing, any tau; the density prefetch stays on for tau = 1 only
-//     (re-reading N_k in the collision leaves no registers for it);
-//   - global addressing (FP32 states of 4 GB and more, FP64), without the prefetch: at 512^3
-//     the step is bound by HBM traffic, and the stash saves the collision's second pull of the
-//     energy populations (12.6 ms against 14.4 ms for the prefetch alone);
-//   - not for FP64 with a collision that re-reads N_k (it would spill).
+// Picks the instantiation for the run-time facts: the address form the state allows, the
+// tau = 1 collision (no re-read of N_k) when 1/tau is exactly 1 with BGK, and the MRT collision
+// (which re-reads N_k, with the load order of tau != 1) when asked for.
+//   - FP32 states under 4 GB: one buffer resource per buffer.  Where the variant has the LDS
+//     stash, the density prefetch stays on for tau = 1 only (re-reading N_k in the collision
+//     leaves no registers for it).
+//   - otherwise (FP64, the GLOBAL variant, states of 4 GB and more) global addressing, with the stash
+//     where the variant asks for it and without the prefetch: at 512^3 the step is bound by
+//     HBM traffic, and the stash saves the collision's second pull of the energy populations
+//     (12.6 ms against 14.4 ms for the prefetch alone); not for FP64 with a collision that
+//     re-reads N_k (it would spill).
 template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool STASH = false,
           bool GLOBAL = false>
 hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Phys& ph,
@@ -238,15 +247,15 @@ hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Ph
     const bool tau1 = ph.omega == 1.0 && !mrt;
     if constexpr (sizeof(S) == 4 && !GLOBAL) {
         if (fits_buffer(g, Q, 4)) {
-            if (tau1) return launch_one<Q, S, R, TX, TY, NTH, PIPE, STASH, true, kTauOne>(src, dst, g, ph, aux, st);
-            if (mrt) return launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, true, kMrt>(src, dst, g, ph, aux, st);
-            return launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, true, kTauAny>(src, dst, g, ph, aux, st);
+            if (tau1) return launch_one<Q, S, R, TX, TY, NTH, PIPE, STASH, kAddrBuf, kTauOne>(src, dst, g, ph, aux, st);
+            if (mrt) return launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, kAddrBuf, kMrt>(src, dst, g, ph, aux, st);
+            return launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, kAddrBuf, kTauAny>(src, dst, g, ph, aux, st);
         }
     }
     constexpr bool kStashAnyTau = STASH && sizeof(S) == 4;
-    if (tau1) return launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, false, kTauOne>(src, dst, g, ph, aux, st);
-    if (mrt) return launch_one<Q, S, R, TX, TY, NTH, PIPE && !kStashAnyTau, kStashAnyTau, false, kMrt>(src, dst, g, ph, aux, st);
-    return launch_one<Q, S, R, TX, TY, NTH, PIPE && !kStashAnyTau, kStashAnyTau, false, kTauAny>(src, dst, g, ph, aux, st);
+    if (tau1) return launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, kAddrGlobal, kTauOne>(src, dst, g, ph, aux, st);
+    if (mrt) return launch_one<Q, S, R, TX, TY, NTH, PIPE && !kStashAnyTau, kStashAnyTau, kAddrGlobal, kMrt>(src, dst, g, ph, aux, st);
+    return launch_one<Q, S, R, TX, TY, NTH, PIPE && !kStashAnyTau, kStashAnyTau, kAddrGlobal, kTauAny>(src, dst, g, ph, aux, st);
 }
 
 }  // namespace
@@ -360,15 +369,15 @@ hipError_t launch_init(int Q, int storage_bytes, void* buf, const double* rho0, 
 }
 
 hipError_t launch_moments(int Q, int storage_bytes, const void* buf, double* scratch, int nx, int ny,
-                          int nz, long long plane, const Phys& ph, int* err, double* rho,
-                          double* us, double* E, double* T, hipStream_t st)
+                          int nz, long long plane, const Phys& ph, const double* eos_p, int* err,
+                          double* rho, double* us, double* E, double* T, hipStream_t st)
 {
     const long long n = (long long)nx * ny * nz;
     const dim3 grid(blocks_for(n, 256)), block(256);
-    if (Q == 19 && storage_bytes == 4) hipLaunchKernelGGL((k_moments_a<19, float>), grid, block, 0, st, (const float*)buf, scratch, nx, ny, nz, plane, ph, err);
-    else if (Q == 19 && storage_bytes == 8) hipLaunchKernelGGL((k_moments_a<19, double>), grid, block, 0, st, (const double*)buf, scratch, nx, ny, nz, plane, ph, err);
-    else if (Q == 9 && storage_bytes == 4) hipLaunchKernelGGL((k_moments_a<9, float>), grid, block, 0, st, (const float*)buf, scratch, nx, ny, nz, plane, ph, err);
-    else if (Q == 9 && storage_bytes == 8) hipLaunchKernelGGL((k_moments_a<9, double>), grid, block, 0, st, (const double*)buf, scratch, nx, ny, nz, plane, ph, err);
+    if (Q == 19 && storage_bytes == 4) hipLaunchKernelGGL((k_moments_a<19, float>), grid, block, 0, st, (const float*)buf, scratch, nx, ny, nz, plane, ph, eos_p, err);
+    else if (Q == 19 && storage_bytes == 8) hipLaunchKernelGGL((k_moments_a<19, double>), grid, block, 0, st, (const double*)buf, scratch, nx, ny, nz, plane, ph, eos_p, err);
+    else if (Q == 9 && storage_bytes == 4) hipLaunchKernelGGL((k_moments_a<9, float>), grid, block, 0, st, (const float*)buf, scratch, nx, ny, nz, plane, ph, eos_p, err);
+    else if (Q == 9 && storage_bytes == 8) hipLaunchKernelGGL((k_moments_a<9, double>), grid, block, 0, st, (const double*)buf, scratch, nx, ny, nz, plane, ph, eos_p, err);
     else return hipErrorInvalidValue;
     if (Q == 19) hipLaunchKernelGGL((k_moments_b<19>), grid, block, 0, st, scratch, nx, ny, nz, ph, rho, us, E, T);
     else hipLaunchKernelGGL((k_moments_b<9>), grid, block, 0, st, scratch, nx, ny, nz, ph, rho, us, E, T);

@@ -22,6 +22,8 @@ struct StepAux {
     const double* __restrict__ maxwell;  // band-limit table (reduced densities)
     double tab_s0, tab_inv_ds;
     int* err;                            // device error word (atomicOr)
+    const double* __restrict__ eos_p;    // tabulated EOS (Phys::eos = 1): reduced pressures
+    const double* __restrict__ eos_coex; // and its coexistence band per row
 };
 
 int step_variants(int Q, int storage_bytes);
@@ -32,8 +34,8 @@ hipError_t launch_init(int Q, int storage_bytes, void* buf, const double* rho0, 
                        const double* T0, int nx, int ny, int nz, long long plane, double c_v,
                        int walls, hipStream_t st);
 hipError_t launch_moments(int Q, int storage_bytes, const void* buf, double* scratch, int nx, int ny,
-                          int nz, long long plane, const Phys& ph, int* err, double* rho,
-                          double* us, double* E, double* T, hipStream_t st);
+                          int nz, long long plane, const Phys& ph, const double* eos_p, int* err,
+                          double* rho, double* us, double* E, double* T, hipStream_t st);
 int reduce_blocks(long long n);
 hipError_t launch_reduce(int Q, int storage_bytes, const void* buf, long long n, long long plane,
                          double* partials, int nblocks, double* out, hipStream_t st);

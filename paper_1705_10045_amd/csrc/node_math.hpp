@@ -31,17 +31,23 @@ __device__ __forceinline__ void moment_sums(const S* pn, const S* pe, double& dr
     for (int k = 0; k < Q; ++k) dE += double(pe[k]);
 }
 
-// T = E / (rho c_V), the van der Waals pressure (section 3) and Phi^2 = rho theta - p, FP64.
-// `ok` is false when the node has left the domain of the EOS (Phi^2 <= 0, rho beyond the pole,
-// non-finite energy).
+// T = E / (rho c_V), the pressure (section 3: the van der Waals EOS, or with TABLE the
+// tabulated one) and Phi^2 = rho theta - p, FP64.  `ok` is false when the node has left the
+// domain of the EOS (Phi^2 <= 0, rho beyond the pole or the table, non-finite energy).
+template <bool TABLE>
 __device__ __forceinline__ void eos_phi2(double dr, double dE, const Phys& ph, unsigned flags,
-                                         double& dT, double& p, double& phi2, bool& ok)
+                                         const StepAux& aux, double& dT, double& p, double& phi2,
+                                         bool& ok)
 {
     dT = dE / (dr * ph.c_v);
     const double Te = (flags & kBaro) ? ph.T0_baro : dT;
-    p = vdw_pressure(dr, Te, ph);
+    bool inside = true;
+    if constexpr (TABLE)
+        p = ph.p_c * table_pressure(dr * ph.inv_rho_c, Te * ph.inv_T_c, ph, aux.eos_p, inside);
+    else
+        p = vdw_pressure(dr, Te, ph);
     phi2 = dr * kTheta - p;
-    ok = phi2 > 0.0 && dr * ph.inv_rho_c < 3.0 && dr > 0.0 && dE == dE && dE < 1e30;
+    ok = inside && phi2 > 0.0 && dr * ph.inv_rho_c < 3.0 && dr > 0.0 && dE == dE && dE < 1e30;
 }
 
 // Force of section 3 in FP64 (a small difference of Phi^2 values) at index e of a plane of
@@ -78,7 +84,7 @@ __device__ __forceinline__ void force_at(const double* pm, const double* p0, con
 // -p div u*, conservative conduction with face conductivity c_V chi (rho_i + rho_j)/2, and the
 // latent-heat term inside the coexistence band.  r0 and t0 are the rho and T planes of the
 // node; rm, tm and rp, tp the values of its neighbours at z - 1 and z + 1 (D = 3).
-template <int D, class R, int W>
+template <int D, class R, int W, bool TABLE = false>
 __device__ __forceinline__ R energy_source(R p, R div, R rho, R T, R rm, const R* r0, R rp,
                                            R tm, const R* t0, R tp, int e, R cond_half,
                                            unsigned flags, const Phys& ph, const StepAux& aux)
@@ -96,8 +102,12 @@ __device__ __forceinline__ R energy_source(R p, R div, R rho, R T, R rm, const R
     if (flags & kLatent) {
         const double Te = (flags & kBaro) ? ph.T0_baro : double(T);
         double r1, r2;
-        if (band_limits(Te * ph.inv_T_c, aux.maxwell, aux.tab_s0, aux.tab_inv_ds, ph.rho_c, r1,
-                        r2)) {
+        bool band;
+        if constexpr (TABLE)
+            band = table_band(Te * ph.inv_T_c, ph, aux.eos_coex, r1, r2);
+        else
+            band = band_limits(Te * ph.inv_T_c, aux.maxwell, aux.tab_s0, aux.tab_inv_ds, ph.rho_c, r1, r2);
+        if (band) {
             const double rd = double(rho);
             if (rd > r1 && rd < r2) dE -= R(ph.rhoQ / (r2 - r1) * rd * double(div));
         }

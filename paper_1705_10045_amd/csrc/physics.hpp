@@ -32,6 +32,12 @@ struct Phys {
     // the third-order moments m
     int collision;
     double mrt_de, mrt_deps, mrt_dq, mrt_dm;
+    // equation of state: 0 the reduced van der Waals EOS; 1 a table of reduced pressure on a
+    // uniform grid (section 3 allows tabulated EOS of real fluids), see table_pressure
+    int eos;
+    int tab_nrho, tab_nT;
+    double tab_rho_min, tab_rho_max, tab_drho;
+    double tab_T_min, tab_T_max, tab_dT;
 };
 
 enum : unsigned { kWallTBottom = 1u, kWallTTop = 2u };
@@ -51,6 +57,50 @@ __host__ __device__ inline double vdw_pressure(double rho, double T, const Phys&
     const double rr = rho * p.inv_rho_c;
     const double tr = T * p.inv_T_c;
     return p.p_c * (8.0 * rr * tr / (3.0 - rr) - 3.0 * rr * rr);
+}
+
+// Tabulated reduced pressure p~(rr, Tr) (rr = rho/rho_c, Tr = T/T_c): the table holds p~ at
+// rho~_i = tab_rho_min + i tab_drho and T~_j = tab_T_min + j tab_dT as tab[j * tab_nrho + i].
+// Cubic Lagrange interpolation in rho~ through the four grid densities around the point (the
+// stencil shifted inward next to the grid's ends), linear in T~ between the two rows around it.
+// `inside` is false (and 0 returned) outside the grid: the node has left the EOS domain.
+__host__ __device__ inline double table_pressure(double rr, double Tr, const Phys& p,
+                                                 const double* __restrict__ tab, bool& inside)
+{
+    inside = rr >= p.tab_rho_min && rr <= p.tab_rho_max && Tr >= p.tab_T_min && Tr <= p.tab_T_max;
+    if (!inside) return 0.0;
+    int j = (int)floor((Tr - p.tab_T_min) / p.tab_dT);
+    j = j > p.tab_nT - 2 ? p.tab_nT - 2 : (j < 0 ? 0 : j);
+    const double u = (Tr - (p.tab_T_min + j * p.tab_dT)) / p.tab_dT;
+    int i0 = (int)floor((rr - p.tab_rho_min) / p.tab_drho) - 1;
+    i0 = i0 > p.tab_nrho - 4 ? p.tab_nrho - 4 : (i0 < 0 ? 0 : i0);
+    const double t = (rr - (p.tab_rho_min + i0 * p.tab_drho)) / p.tab_drho;
+    // Lagrange basis on grid nodes i0 .. i0 + 3 at offset t from node i0
+    const double w0 = -(t - 1.0) * (t - 2.0) * (t - 3.0) / 6.0;
+    const double w1 = t * (t - 2.0) * (t - 3.0) / 2.0;
+    const double w2 = -t * (t - 1.0) * (t - 3.0) / 2.0;
+    const double w3 = t * (t - 1.0) * (t - 2.0) / 6.0;
+    const double* a = tab + (long long)j * p.tab_nrho + i0;
+    const double* b = a + p.tab_nrho;
+    const double lo = w0 * a[0] + w1 * a[1] + w2 * a[2] + w3 * a[3];
+    const double hi = w0 * b[0] + w1 * b[1] + w2 * b[2] + w3 * b[3];
+    return (1.0 - u) * lo + u * hi;
+}
+
+// Coexistence band (rho_1, rho_2) of a tabulated EOS at reduced temperature Tr, linear in T~
+// between the rows of coex (coex[2j] <= coex[2j + 1], reduced densities).  False outside the
+// table's temperature range.
+__host__ __device__ inline bool table_band(double Tr, const Phys& p,
+                                           const double* __restrict__ coex, double& r1,
+                                           double& r2)
+{
+    if (!(Tr >= p.tab_T_min && Tr <= p.tab_T_max)) return false;
+    int j = (int)floor((Tr - p.tab_T_min) / p.tab_dT);
+    j = j > p.tab_nT - 2 ? p.tab_nT - 2 : (j < 0 ? 0 : j);
+    const double u = (Tr - (p.tab_T_min + j * p.tab_dT)) / p.tab_dT;
+    r1 = p.rho_c * ((1.0 - u) * coex[2 * j] + u * coex[2 * j + 2]);
+    r2 = p.rho_c * ((1.0 - u) * coex[2 * j + 1] + u * coex[2 * j + 3]);
+    return true;
 }
 
 // Coexistence densities (rho_1, rho_2) of the band at reduced temperature Tr, cubic Lagrange

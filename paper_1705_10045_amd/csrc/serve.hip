@@ -12,6 +12,13 @@
 // Host side: first-fit allocation of slot buffers inside one arena allocated at creation
 // (admission by footprint never calls the allocator of the runtime), tickets, and the
 // completion bookkeeping read back after each replay.
+//
+// Overlap: replays run on the pool's stream; admissions (upload, initial state) and
+// collections (moments, download) run on a second stream of the same (default) priority.  A
+// replay may be left in flight (lbm_pool_run_async): the slot table travels through pinned
+// host buffers, the next call waits for the replay and its readback, and only then rewrites
+// the device table.  Meanwhile admissions touch only free arena blocks and slots that the
+// replay in flight does not advance, and collections only finished (inactive) slots.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -80,13 +87,15 @@ k_pool_step(const SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ h
         aux.tab_s0 = s0;
         aux.tab_inv_ds = inv_ds;
         aux.err = errs + lo;
+        aux.eos_p = nullptr;
+        aux.eos_coex = nullptr;
         // each request's own collision: tau = 1 (with the density prefetch) or general; both
         // share the workgroup's LDS
         if (ph.omega == 1.0)
-            step_tile<19, float, float, kPoolTX, kPoolTY, kPoolThreads, true, true, kTauOne, true, false>(
+            step_tile<19, float, float, kPoolTX, kPoolTY, kPoolThreads, true, kAddrBuf, kTauOne, true, false>(
                 lds, src, dst, g, ph, aux, local);
         else
-            step_tile<19, float, float, kPoolTX, kPoolTY, kPoolThreads, false, true, kTauAny, true, false>(
+            step_tile<19, float, float, kPoolTX, kPoolTY, kPoolThreads, false, kAddrBuf, kTauAny, true, false>(
                 lds, src, dst, g, ph, aux, local);
     }
 }
@@ -118,8 +127,16 @@ struct PoolSlot {
 
 struct lbm_pool {
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;            // replays
     bool own_stream = false;
+    hipStream_t side = nullptr;              // admissions and collections
+    SlotDesc* h_up = nullptr;                // pinned: the table as uploaded before a replay
+    PoolHeader* h_hdr = nullptr;             // pinned: its header
+    SlotDesc* h_rb = nullptr;                // pinned: the table read back after a replay
+    int* h_errs = nullptr;                   // pinned: the error words read back after a replay
+    hipEvent_t done = nullptr;               // end of the replay in flight and of its readback
+    bool in_flight = false;
+    std::vector<long long> launched;         // ticket in each slot when that replay was launched
     size_t budget = 0, in_use = 0;
     char* arena = nullptr;
     std::map<size_t, size_t> free_blocks;   // offset -> size, coalesced
@@ -133,7 +150,6 @@ struct lbm_pool {
     double tab_s0 = 0, tab_inv_ds = 0;
     double* d_staging = nullptr;             // initial fields of a request (5 n doubles)
     double* d_scratch = nullptr;             // moment scratch (10 n doubles)
-    PoolHeader hdr{0, 0};                    // host copy of the device header (persistent for async copies)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool dirty = true;
@@ -209,11 +225,15 @@ lbm_status upload_table(lbm_pool* p)
             d.ntiles = 0;
         }
     }
-    p->hdr.nslots = nslots;
-    p->hdr.total_tiles = total;
-    hipError_t e = hipMemcpyAsync(p->d_slots, p->table.data(), sizeof(SlotDesc) * p->max_slots,
+    // staged in pinned memory: the copies are truly asynchronous, and the host mirror may change
+    // (admissions) before they have run; the pinned copy is rewritten only after the next
+    // replay, which the stream orders after these copies, has completed
+    p->h_hdr->nslots = nslots;
+    p->h_hdr->total_tiles = total;
+    memcpy(p->h_up, p->table.data(), sizeof(SlotDesc) * p->max_slots);
+    hipError_t e = hipMemcpyAsync(p->d_slots, p->h_up, sizeof(SlotDesc) * p->max_slots,
                                   hipMemcpyHostToDevice, p->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(p->d_hdr, &p->hdr, sizeof(PoolHeader), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->d_hdr, p->h_hdr, sizeof(PoolHeader), hipMemcpyHostToDevice, p->stream);
     if (e != hipSuccess) return hip_fail(e, "pool table upload");
     p->dirty = false;
     return LBM_OK;
@@ -234,6 +254,59 @@ lbm_status capture_graph(lbm_pool* p)
     if (e != hipSuccess) return hip_fail(e, "graph capture end");
     e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    return LBM_OK;
+}
+
+// Waits for the replay in flight and its readback, then takes over the new state of every slot
+// that the replay advanced (slots admitted or collected meanwhile keep their host state) and
+// records the requests that finished or left the EOS domain.
+lbm_status finish_replay(lbm_pool* p)
+{
+    if (!p->in_flight) return LBM_OK;
+    p->in_flight = false;
+    const hipError_t e = hipEventSynchronize(p->done);
+    if (e != hipSuccess) return hip_fail(e, "pool replay");
+    for (int s = 0; s < p->max_slots; ++s) {
+        PoolSlot& ps = p->slots[s];
+        if (!ps.used || ps.ticket != p->launched[s]) continue;
+        SlotDesc& d = p->table[s];
+        const SlotDesc& r = p->h_rb[s];
+        d.parity = r.parity;
+        d.active = r.active;
+        d.remaining = r.remaining;
+        d.steps_done = r.steps_done;
+        if (!p->finished.count(ps.ticket)) {
+            if (p->h_errs[s]) p->finished[ps.ticket] = LBM_EUNSTABLE;
+            else if (!r.active) p->finished[ps.ticket] = LBM_OK;
+        }
+        // a slot that finished no longer contributes tiles: rebuild the work list
+        if (!r.active) p->dirty = true;
+    }
+    return LBM_OK;
+}
+
+// Waits for the previous replay (if any), refreshes the table and enqueues the next replay
+// with the readback of its table behind it.
+lbm_status launch_replay(lbm_pool* p)
+{
+    lbm_status st = finish_replay(p);
+    if (st != LBM_OK) return st;
+    if (p->dirty) {
+        st = upload_table(p);
+        if (st != LBM_OK) return st;
+    }
+    bool any = false;
+    for (int s = 0; s < p->max_slots; ++s) any = any || (p->slots[s].used && p->table[s].active);
+    if (!any) return LBM_OK;
+    for (int s = 0; s < p->max_slots; ++s) p->launched[s] = p->slots[s].used ? p->slots[s].ticket : -1;
+    hipError_t e = hipGraphLaunch(p->exec, p->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->h_rb, p->d_slots, sizeof(SlotDesc) * p->max_slots, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->h_errs, p->d_errs, sizeof(int) * p->max_slots, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipEventRecord(p->done, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "pool replay launch");
+    p->in_flight = true;
     return LBM_OK;
 }
 
@@ -272,8 +345,15 @@ lbm_status lbm_pool_create(size_t hbm_budget_bytes, int max_slots, int steps_per
     p->slots.assign(max_slots, PoolSlot());
     p->table.assign(max_slots, SlotDesc());
     memset(p->table.data(), 0, sizeof(SlotDesc) * max_slots);
+    p->launched.assign(max_slots, -1);
     const long long nmax = (long long)kPoolMaxEdge * kPoolMaxEdge * kPoolMaxEdge;
-    hipError_t e = hipMalloc((void**)&p->arena, p->budget);
+    hipError_t e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_up, sizeof(SlotDesc) * max_slots, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_rb, sizeof(SlotDesc) * max_slots, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_hdr, sizeof(PoolHeader), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_errs, sizeof(int) * max_slots, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->arena, p->budget);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_slots, sizeof(SlotDesc) * max_slots);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_hdr, sizeof(PoolHeader));
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_errs, sizeof(int) * max_slots);
@@ -316,8 +396,10 @@ lbm_status lbm_pool_submit(lbm_pool* p, const lbm_params* params, const double* 
         return LBM_EINVAL;
     }
     if (params->walls || params->gravity[0] != 0.0 || params->gravity[1] != 0.0 ||
-        params->gravity[2] != 0.0 || params->collision != LBM_COLLISION_BGK) {
-        set_error("pool requests are periodic boxes without gravity, with the BGK collision");
+        params->gravity[2] != 0.0 || params->collision != LBM_COLLISION_BGK ||
+        params->eos != LBM_EOS_VDW) {
+        set_error("pool requests are periodic boxes without gravity, with the BGK collision and "
+                  "the van der Waals EOS");
         return LBM_EINVAL;
     }
     st = validate_fields(*params, rho0, u0, T0);
@@ -351,16 +433,19 @@ lbm_status lbm_pool_submit(lbm_pool* p, const lbm_params* params, const double* 
     d.active = 1;
     d.remaining = nsteps;
     const long long n = (long long)params->nx * params->ny * params->nz;
-    hipError_t e = hipMemsetAsync(p->arena + off, 0, 2 * half_al, p->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(p->d_errs + slot, 0, sizeof(int), p->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(p->d_staging, rho0, sizeof(double) * n, hipMemcpyHostToDevice, p->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(p->d_staging + n, u0, sizeof(double) * 3 * n, hipMemcpyHostToDevice, p->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(p->d_staging + 4 * n, T0, sizeof(double) * n, hipMemcpyHostToDevice, p->stream);
+    // on the side stream: a replay in flight does not touch this free arena block or this
+    // slot's error word (the slot is not active on the device)
+    hipError_t e = hipMemsetAsync(p->arena + off, 0, 2 * half_al, p->side);
+    if (e == hipSuccess) e = hipMemsetAsync(p->d_errs + slot, 0, sizeof(int), p->side);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->d_staging, rho0, sizeof(double) * n, hipMemcpyHostToDevice, p->side);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->d_staging + n, u0, sizeof(double) * 3 * n, hipMemcpyHostToDevice, p->side);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->d_staging + 4 * n, T0, sizeof(double) * n, hipMemcpyHostToDevice, p->side);
     if (e == hipSuccess)
         e = launch_init(19, 4, d.buf[0], p->d_staging, p->d_staging + n, p->d_staging + 4 * n, params->nx,
-                        params->ny, params->nz, d.geom.plane, params->c_v, 0, p->stream);
-    // the staging buffer is reused by the next submission: wait for this upload
-    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+                        params->ny, params->nz, d.geom.plane, params->c_v, 0, p->side);
+    // the staging buffer is reused by the next submission, and the next replay must find the
+    // initial state in place: wait for this upload (not for the replay in flight)
+    if (e == hipSuccess) e = hipStreamSynchronize(p->side);
     if (e != hipSuccess) {
         arena_free(p, off, 2 * half_al);
         ps = PoolSlot();
@@ -372,36 +457,22 @@ lbm_status lbm_pool_submit(lbm_pool* p, const lbm_params* params, const double* 
     return LBM_OK;
 }
 
+lbm_status lbm_pool_run_async(lbm_pool* p)
+{
+    clear_error();
+    if (!p) { set_error("pool is NULL"); return LBM_EINVAL; }
+    if (lbm_status sd = use_device(p->device); sd != LBM_OK) return sd;
+    return launch_replay(p);
+}
+
 lbm_status lbm_pool_run(lbm_pool* p)
 {
     clear_error();
     if (!p) { set_error("pool is NULL"); return LBM_EINVAL; }
     if (lbm_status sd = use_device(p->device); sd != LBM_OK) return sd;
-    if (p->dirty) {
-        lbm_status st = upload_table(p);
-        if (st != LBM_OK) return st;
-    }
-    bool any = false;
-    for (int s = 0; s < p->max_slots; ++s) any = any || (p->slots[s].used && p->table[s].active);
-    if (!any) return LBM_OK;
-    hipError_t e = hipGraphLaunch(p->exec, p->stream);
-    std::vector<int> errs(p->max_slots);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(p->table.data(), p->d_slots, sizeof(SlotDesc) * p->max_slots, hipMemcpyDeviceToHost, p->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(errs.data(), p->d_errs, sizeof(int) * p->max_slots, hipMemcpyDeviceToHost, p->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
-    if (e != hipSuccess) return hip_fail(e, "pool replay");
-    for (int s = 0; s < p->max_slots; ++s) {
-        PoolSlot& ps = p->slots[s];
-        if (!ps.used || p->finished.count(ps.ticket)) continue;
-        if (errs[s]) p->finished[ps.ticket] = LBM_EUNSTABLE;
-        else if (!p->table[s].active) p->finished[ps.ticket] = LBM_OK;
-    }
-    // slots that finished no longer contribute tiles: rebuild the work list before the next replay
-    for (int s = 0; s < p->max_slots; ++s)
-        if (p->slots[s].used && !p->table[s].active) { p->dirty = true; break; }
-    return LBM_OK;
+    lbm_status st = launch_replay(p);
+    if (st == LBM_OK) st = finish_replay(p);
+    return st;
 }
 
 lbm_status lbm_pool_poll(lbm_pool* p, long long ticket, int* done, lbm_status* result)
@@ -432,14 +503,15 @@ lbm_status lbm_pool_collect(lbm_pool* p, long long ticket, double* rho, double* 
     double* scr = p->d_scratch;
     double* d_us = scr + 7 * n;
     int* d_err = p->d_errs + s;
+    // on the side stream: the slot has finished, so a replay in flight does not advance it
     hipError_t e = launch_moments(19, 4, d.buf[d.parity], scr, ps.params.nx, ps.params.ny, ps.params.nz,
-                                  d.geom.plane, d.phys, d_err, nullptr, u_star ? d_us : nullptr, nullptr,
-                                  nullptr, p->stream);
-    if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, scr, sizeof(double) * n, hipMemcpyDeviceToHost, p->stream);
-    if (e == hipSuccess && u_star) e = hipMemcpyAsync(u_star, d_us, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, p->stream);
-    if (e == hipSuccess && E) e = hipMemcpyAsync(E, scr + 4 * n, sizeof(double) * n, hipMemcpyDeviceToHost, p->stream);
-    if (e == hipSuccess && T) e = hipMemcpyAsync(T, scr + 5 * n, sizeof(double) * n, hipMemcpyDeviceToHost, p->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+                                  d.geom.plane, d.phys, nullptr, d_err, nullptr, u_star ? d_us : nullptr,
+                                  nullptr, nullptr, p->side);
+    if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, scr, sizeof(double) * n, hipMemcpyDeviceToHost, p->side);
+    if (e == hipSuccess && u_star) e = hipMemcpyAsync(u_star, d_us, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, p->side);
+    if (e == hipSuccess && E) e = hipMemcpyAsync(E, scr + 4 * n, sizeof(double) * n, hipMemcpyDeviceToHost, p->side);
+    if (e == hipSuccess && T) e = hipMemcpyAsync(T, scr + 5 * n, sizeof(double) * n, hipMemcpyDeviceToHost, p->side);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->side);
     if (e != hipSuccess) return hip_fail(e, "collect");
     const lbm_status result = f->second;
     arena_free(p, ps.offset, ps.bytes);
@@ -473,6 +545,7 @@ lbm_status lbm_pool_destroy(lbm_pool* p)
     // release everything even if the device reports an error: nothing here can be retried
     (void)hipSetDevice(p->device);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
+    if (p->side) (void)hipStreamSynchronize(p->side);
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->arena) (void)hipFree(p->arena);
@@ -482,6 +555,12 @@ lbm_status lbm_pool_destroy(lbm_pool* p)
     if (p->d_staging) (void)hipFree(p->d_staging);
     if (p->d_scratch) (void)hipFree(p->d_scratch);
     if (p->d_table) (void)hipFree(p->d_table);
+    if (p->h_up) (void)hipHostFree(p->h_up);
+    if (p->h_rb) (void)hipHostFree(p->h_rb);
+    if (p->h_hdr) (void)hipHostFree(p->h_hdr);
+    if (p->h_errs) (void)hipHostFree(p->h_errs);
+    if (p->done) (void)hipEventDestroy(p->done);
+    if (p->side) (void)hipStreamDestroy(p->side);
     if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
     delete p;
     return LBM_OK;

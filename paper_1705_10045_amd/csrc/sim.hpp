@@ -24,6 +24,8 @@ struct lbm_sim {
     double* d_table = nullptr;
     double* d_partials = nullptr;
     double* d_scratch = nullptr;         // moment scratch (7n doubles), allocated on first use
+    double* d_eos_p = nullptr;           // tabulated EOS: reduced pressures and band per row
+    double* d_eos_coex = nullptr;
     int red_blocks = 1;
     int tile_x = 0, tile_y = 0;
     int variant = 0;                     // tile shape of the fused step (see step_tile)

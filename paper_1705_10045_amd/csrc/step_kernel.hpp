@@ -90,18 +90,25 @@ __device__ __forceinline__ void region_slot(int s, int& rx, int& ry)
     rx = c < HALO ? c : RW - 2 * HALO + c;
 }
 
-// Access to population (set*Q + k) at node i of the two buffers.  With BUF the state (< 4 GB)
-// is addressed through buffer resources: the node offset is a 32-bit per-lane byte offset and
-// the plane offset of the population a scalar offset, so no per-access 64-bit address
-// arithmetic is spent.  Otherwise global pointers with a scalar plane base.  Stores are marked
-// non-temporal
-// (nothing in the step reads them back), so they do not displace the halo and re-read data the
-// step still needs from L2.
-template <class S, bool BUF>
+// Access to population (set*Q + k) at node i of the two buffers, in one of two address forms
+// (ADDR), both with 32-bit per-lane node offsets (a plane is under 4 GB):
+//   0 (kAddrGlobal): global pointers with a scalar plane base;
+//   1 (kAddrBuf):    one buffer resource per buffer (the state is under 4 GB): the node offset
+//                    is the lane's 32-bit offset and the population's plane offset a scalar one.
+// Buffer instructions take 32-bit offsets against a scalar base, where global loads carry a
+// 64-bit address per lane; at 128^3 and 256^3 the buffer form measured 16-26% faster.  Stores
+// are marked non-temporal (nothing in the step reads them back), so they do not displace the
+// halo and re-read data the step still needs from L2.
+enum AddrMode : int { kAddrGlobal = 0, kAddrBuf = 1 };
+
+// Which extensions of the paper's periodic step an instantiation carries (see step_tile).
+enum ExtMode : int { kExtNone = 0, kExtWalls = 1, kExtTable = 2 };
+
+template <class S, int ADDR>
 struct PopIO;
 
 template <class S>
-struct PopIO<S, false> {
+struct PopIO<S, kAddrGlobal> {
     const S* __restrict__ src;
     S* __restrict__ dst;
     long long plane;
@@ -120,32 +127,51 @@ struct PopIO<S, false> {
     }
 };
 
-// Offsets are formed in unsigned 32-bit arithmetic (the host allows this form only for states
-// under 4 GB, so no offset wraps) and handed to the builtins as their bit pattern.
-template <>
-struct PopIO<float, true> {
+// Raw buffer access of one FP32 or FP64 value; offsets are formed in unsigned 32-bit arithmetic
+// by the callers (the host picks a form only where no offset wraps) and handed over as their
+// bit pattern.  Bit 1 of the cache-policy operand is the non-temporal hint.
+namespace bufio {
+constexpr int kNT = 2;
+constexpr int kWord3 = 0x00020000;
+template <class S>
+__device__ __forceinline__ S load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    const int v = __builtin_bit_cast(int, voff), so = __builtin_bit_cast(int, soff);
+    if constexpr (sizeof(S) == 4)
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, v, so, 0));
+    else
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, v, so, 0));
+}
+template <class S>
+__device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, S x)
+{
+    const int v = __builtin_bit_cast(int, voff), so = __builtin_bit_cast(int, soff);
+    if constexpr (sizeof(S) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, so, kNT);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, x),
+                                              r, v, so, kNT);
+}
+}  // namespace bufio
+
+template <class S>
+struct PopIO<S, kAddrBuf> {
     __amdgpu_buffer_rsrc_t rs, rd;
     unsigned plane_bytes;
-    __device__ PopIO(const float* s, float* d, long long p, int npk)
+    __device__ PopIO(const S* s, S* d, long long p, int npk)
     {
-        const unsigned bytes = (unsigned)((unsigned long long)p * (unsigned)npk * 4u);
-        rs = __builtin_amdgcn_make_buffer_rsrc((void*)s, (short)0, __builtin_bit_cast(int, bytes), 0x00020000);
-        rd = __builtin_amdgcn_make_buffer_rsrc((void*)d, (short)0, __builtin_bit_cast(int, bytes), 0x00020000);
-        plane_bytes = (unsigned)((unsigned long long)p * 4u);
+        const unsigned bytes = (unsigned)((unsigned long long)p * (unsigned)npk * sizeof(S));
+        rs = __builtin_amdgcn_make_buffer_rsrc((void*)s, (short)0, __builtin_bit_cast(int, bytes), bufio::kWord3);
+        rd = __builtin_amdgcn_make_buffer_rsrc((void*)d, (short)0, __builtin_bit_cast(int, bytes), bufio::kWord3);
+        plane_bytes = (unsigned)((unsigned long long)p * sizeof(S));
     }
-    // cache-policy operand of the buffer instructions: bit 1 is the non-temporal hint
-    static constexpr int kNT = 2;
-    __device__ __forceinline__ float load(int pk, int i) const
+    __device__ __forceinline__ S load(int pk, int i) const
     {
-        const int voff = __builtin_bit_cast(int, (unsigned)i * 4u);
-        const int soff = __builtin_bit_cast(int, (unsigned)pk * plane_bytes);
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+        return bufio::load<S>(rs, (unsigned)i * (unsigned)sizeof(S), (unsigned)pk * plane_bytes);
     }
-    __device__ __forceinline__ void store(int pk, int i, float v) const
+    __device__ __forceinline__ void store(int pk, int i, S v) const
     {
-        const int voff = __builtin_bit_cast(int, (unsigned)i * 4u);
-        const int soff = __builtin_bit_cast(int, (unsigned)pk * plane_bytes);
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rd, voff, soff, kNT);
+        bufio::store<S>(rd, (unsigned)i * (unsigned)sizeof(S), (unsigned)pk * plane_bytes, v);
     }
 };
 
@@ -200,9 +226,11 @@ struct TileLds {
 // thread's first moment and force slots are its own collision node and the own node's
 // moments and force stay in registers between the stages.
 //
-// EXT: walls normal to z (Phys::walls: bounce-back pulls next to them, no stages on the planes
+// EXT (kExtNone, kExtWalls, kExtTable): walls normal to z (Phys::walls: bounce-back pulls next
+// to them, no stages on the planes
 // beyond them, mirror values for the stages next to them) and the body force rho g; the
-// instantiation without EXT is the periodic step with none of that code.
+// instantiation without EXT is the periodic step with none of that code; kExtTable adds the
+// tabulated equation of state (Phys::eos = 1) to everything kExtWalls has.
 //
 // PIPE: the pulls of the next plane's first moment slot are issued right after the current
 // plane's sums, so they are in flight during the force and collision stages.  STASH (D3Q19):
@@ -211,15 +239,14 @@ struct TileLds {
 // plane in registers until its collision has read the older plane of the same ring slot, then
 // moves it there).  With the stash, the prefetch covers the density populations only (the
 // energy pulls already occupy registers until the collision).
-template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool BUF, int NMODE,
-          bool STASH, bool EXT>
+template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, int ADDR, int NMODE,
+          bool STASH, int EXT>
 __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
                                           const S* __restrict__ src, S* __restrict__ dst,
                                           const StepGeom& g, const Phys& ph, const StepAux& aux,
                                           const int lb)
 {
-    static_assert(!BUF || sizeof(S) == 4, "buffer addressing is used for FP32 populations");
-    PopIO<S, BUF> io(src, dst, g.plane, 2 * Q);
+    PopIO<S, ADDR> io(src, dst, g.plane, 2 * Q);
     using L = Lattice<Q>;
     constexpr int D = L::D;
     constexpr int ZH = (D == 3) ? 2 : 0;    // lead of the moment stage over the collision
@@ -231,7 +258,8 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
     constexpr bool kStash = Lds::kStash;
     // walls and body force exist only in the EXT instantiation (the periodic one has none of
     // their code)
-    const bool has_walls = EXT && D == 3 && ph.walls != 0;
+    const bool has_walls = EXT != kExtNone && D == 3 && ph.walls != 0;
+    constexpr bool kTable = EXT == kExtTable;
     constexpr bool kFiveRing = D == 3;   // no barrier closes an iteration
     constexpr int RING = Lds::RING, PR = Lds::PR, JR = Lds::JR, UH = Lds::UH, UZ = Lds::UZ;
     // moment slots beyond the first NTH go to threads without collision work when they fit
@@ -375,7 +403,7 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
         double dr, djx, djy, djz, dE, dT, p, phi2;
         bool ok;
         moment_sums<Q>(pn, pe, dr, djx, djy, djz, dE);
-        eos_phi2(dr, dE, ph, flags, dT, p, phi2, ok);
+        eos_phi2<kTable>(dr, dE, ph, flags, aux, dT, p, phi2, ok);
         if (!ok) {
             atomicOr(aux.err, 1);
             phi2 = 0.0;
@@ -412,7 +440,7 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
     // planes beyond a wall: no pulls, moments or force; the stages next to the wall use the
     // mirror values instead
     auto beyond_wall = [&](int z) { return has_walls && (z < 0 || z >= g.nz); };
-    const bool has_g = EXT && (ph.g[0] != 0.0 || ph.g[1] != 0.0 || ph.g[2] != 0.0);
+    const bool has_g = EXT != kExtNone && (ph.g[0] != 0.0 || ph.g[1] != 0.0 || ph.g[2] != 0.0);
 
     // the own node's pulls for the collision at plane zc (moving directions; the rest ones
     // follow from the balances); with the stash the energy populations come from LDS
@@ -497,7 +525,7 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
         R div = R(0.5) * (sUh[0][suc][of + 1] - sUh[0][suc][of - 1]) +
                 R(0.5) * (sUh[1][suc][of + FX] - sUh[1][suc][of - FX]);
         if constexpr (D == 3) div += R(0.5) * (uzp - uzm);
-        const R dE = energy_source<D, R, FX>(p, div, rho, T, rzm, sRho[sc], rzp, tzm, sT[sc], tzp,
+        const R dE = energy_source<D, R, FX, kTable>(p, div, rho, T, rzm, sRho[sc], rzp, tzm, sT[sc], tzp,
                                              of, cond_half, flags, ph, aux);
 
         NodeCollision<Q, S, R, WN, NMODE == kMrt> c;
@@ -629,14 +657,14 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
     if constexpr (kFiveRing) __syncthreads();
 }
 
-template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool BUF, int NMODE,
-          bool STASH, bool EXT>
+template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, int ADDR, int NMODE,
+          bool STASH, int EXT>
 __global__ void __launch_bounds__(NTH)
 k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const Phys ph,
        const StepAux aux)
 {
     __shared__ TileLds<Q, S, R, TX, TY, STASH> lds;
-    step_tile<Q, S, R, TX, TY, NTH, PIPE, BUF, NMODE, STASH, EXT>(
+    step_tile<Q, S, R, TX, TY, NTH, PIPE, ADDR, NMODE, STASH, EXT>(
         lds, src, dst, g, ph, aux, xcd_logical_block(blockIdx.x, gridDim.x, g.resident));
 }
 

@@ -43,11 +43,19 @@ class lbm_params(ctypes.Structure):
         ("collision", ctypes.c_int),
         ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double), ("s_q", ctypes.c_double),
         ("s_m", ctypes.c_double),
+        ("eos", ctypes.c_int),
+        ("eos_p", ctypes.POINTER(ctypes.c_double)), ("eos_coex", ctypes.POINTER(ctypes.c_double)),
+        ("eos_nrho", ctypes.c_int), ("eos_nT", ctypes.c_int),
+        ("eos_rho_min", ctypes.c_double), ("eos_rho_max", ctypes.c_double),
+        ("eos_T_min", ctypes.c_double), ("eos_T_max", ctypes.c_double),
     ]
 
 
 LBM_COLLISION_BGK = 0
 LBM_COLLISION_MRT = 1
+
+LBM_EOS_VDW = 0
+LBM_EOS_TABLE = 1
 
 LBM_WALL_T_BOTTOM = 1
 LBM_WALL_T_TOP = 2
@@ -81,6 +89,7 @@ _SIGNATURES = [
     ("lbm_pool_submit", _ST, [_P, ctypes.POINTER(lbm_params), _D, _D, _D, ctypes.c_longlong,
                               ctypes.POINTER(ctypes.c_longlong)]),
     ("lbm_pool_run", _ST, [_P]),
+    ("lbm_pool_run_async", _ST, [_P]),
     ("lbm_pool_poll", _ST, [_P, ctypes.c_longlong, ctypes.POINTER(ctypes.c_int),
                             ctypes.POINTER(ctypes.c_int)]),
     ("lbm_pool_collect", _ST, [_P, ctypes.c_longlong, _D, _D, _D, _D]),
@@ -144,6 +153,21 @@ def make_params(Q, shape, physics, storage_bytes=4):
     p.collision = int(physics.get("collision", LBM_COLLISION_BGK))
     for k in ("s_e", "s_eps", "s_q", "s_m"):
         setattr(p, k, float(physics.get(k, 1.0)))
+    # optional tabulated equation of state: physics["eos_table"] = dict(p=(nT, nrho) reduced
+    # pressures, coex=(nT, 2) reduced band limits, rho_range=(min, max), T_range=(min, max));
+    # the arrays are kept on the params object until lbm_init has read them
+    table = physics.get("eos_table")
+    if table:
+        tp = np.ascontiguousarray(table["p"], dtype=np.float64)
+        tc = np.ascontiguousarray(table["coex"], dtype=np.float64)
+        if tp.ndim != 2 or tc.shape != (tp.shape[0], 2):
+            raise ValueError("eos_table p must be (nT, nrho) and coex (nT, 2)")
+        p.eos = LBM_EOS_TABLE
+        p.eos_p, p.eos_coex = _dp(tp), _dp(tc)
+        p.eos_nT, p.eos_nrho = tp.shape
+        p.eos_rho_min, p.eos_rho_max = (float(v) for v in table["rho_range"])
+        p.eos_T_min, p.eos_T_max = (float(v) for v in table["T_range"])
+        p._keep = (tp, tc)
     return p
 
 
@@ -347,6 +371,10 @@ def lbm_pool_run(pool):
     return _check(lib().lbm_pool_run(pool))
 
 
+def lbm_pool_run_async(pool):
+    return _check(lib().lbm_pool_run_async(pool))
+
+
 def lbm_pool_poll(pool, ticket):
     done = ctypes.c_int()
     res = ctypes.c_int()
@@ -394,6 +422,9 @@ class Pool:
 
     def run(self):
         lbm_pool_run(self._h)
+
+    def run_async(self):
+        lbm_pool_run_async(self._h)
 
     def poll(self, ticket):
         return lbm_pool_poll(self._h, ticket)

@@ -4,8 +4,10 @@ Requests (independent D3Q19 thermal two-phase simulations of uneven lattice size
 time.  The loop admits every arrived request that fits a free slot and the remaining HBM
 budget (first fit in arrival order), advances all admitted requests together with one pool
 replay (one batched launch per step, replayed from a HIP graph), collects the finished ones
-and frees their slots for the requests still waiting.  Time-to-result of a request is its
-completion time minus its arrival time.
+and frees their slots for the requests still waiting.  With the device pool the replay is left
+in flight while the loop collects and admits, so host work and uploads overlap the device's
+steps.  Time-to-result of a request is the time its result fields reach the caller minus its
+arrival time.
 
 The scheduler is written against a small executor interface (submit / run / poll / collect /
 stats) so that its bookkeeping can be exercised without a device; `PoolExecutor` is the real
@@ -68,7 +70,9 @@ class PoolExecutor:
         return ticket
 
     def run(self):
-        self.pool.run()
+        # the replay stays in flight while the loop collects, admits and uploads (on the pool's
+        # second stream); the next call waits for it
+        self.pool.run_async()
 
     def poll(self, ticket):
         return self.pool.poll(ticket)

@@ -1,0 +1,91 @@
+"""The full-size configurations on the GPU: states at the top of the buffer-resource range and
+beyond it, the 256^3 spinodal with FP64 populations against the oracle, and the 512^3 pool
+boiling over 10,000 steps.  Each test prints the case before its device work."""
+import numpy as np
+import pytest
+
+from paper_1705_10045_amd import inputs as I
+from paper_1705_10045_amd import lbm
+from parity import describe, rel_errors, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+# pool-boiling boxes whose FP32 state (2 sets x 19 x 4 B per node and buffer) lies just under
+# the 4 GB that one buffer resource addresses (the top of the buffer form's range: offsets up to
+# 4.2e9 bytes) and beyond it (global addressing)
+NEAR_4GB = (96, 320, 900)
+BEYOND_4GB = (96, 320, 1024)
+
+
+def _moments_after(case, steps, variant=None, storage=4):
+    with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"],
+                 storage_bytes=storage) as s:
+        if variant is not None:
+            s.set_launch(variant, 0)
+        s.step(steps)
+        return s.moments()
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.8])
+@pytest.mark.parametrize("shape", [NEAR_4GB, BEYOND_4GB])
+def test_large_state_variants_bitwise(tau, shape):
+    """Just under 4 GB the default launches (variants 0 and 1) address the state through one
+    buffer resource per buffer, with scalar plane offsets up to 4.2e9 bytes; variant 5 keeps
+    global addressing.  Beyond 4 GB all use global addressing.  Same per-node arithmetic, so the
+    fields agree bit for bit."""
+    case = I.pool_boiling_3d(shape=shape, params=I.physics(tau=tau))
+    n = case["rho0"].size
+    assert (2 * 19 * 4 * n < (1 << 32)) == (shape == NEAR_4GB)
+    print("large state: pool boiling %s tau %g, variants 0, 1, 5" % (shape, tau), flush=True)
+    ref = _moments_after(case, 4, 5)
+    for v in (0, 1):
+        m = _moments_after(case, 4, v)
+        for k in m:
+            assert np.array_equal(m[k], ref[k]), (v, k)
+
+
+@pytest.mark.parametrize("shape", [NEAR_4GB, BEYOND_4GB])
+def test_large_state_against_oracle(shape):
+    case = I.pool_boiling_3d(shape=shape)
+    print("large state: pool boiling %s vs oracle, 3 steps" % (shape,), flush=True)
+    g = _moments_after(case, 3)
+    o, _ = run_oracle(case, 3)
+    errs = rel_errors(g, o)
+    describe("pool boiling %s 4B, 3 steps" % (shape,), errs)
+    assert max(errs.values()) < 1e-5
+
+
+def test_spinodal_256_fp64_storage_against_oracle():
+    """The 256^3 spinodal (T~ 0.75, rho = 1 (1 + 0.02 N(0, 1))) with FP64 populations, in the
+    launch the benchmark times for that storage, against the oracle after 20 steps."""
+    case = I.spinodal_3d(n=256, Tr=0.75, rho_mean=1.0, sigma=0.02)
+    print("spinodal 256^3 FP64 vs oracle, 20 steps", flush=True)
+    g = _moments_after(case, 20, storage=8)
+    o, _ = run_oracle(case, 20)
+    errs = rel_errors(g, o)
+    describe("spinodal 256^3 8B, 20 steps", errs)
+    assert max(errs.values()) < 1e-11
+
+
+def test_pool_boiling_512_for_10000_steps():
+    """The 512^3 pool boiling workload at its listed length: 10,000 steps without leaving the
+    EOS domain (the device error word), every field finite, mass conserved to FP32 storage
+    rounding, and the internal energy rising: the bottom wall (T~ 0.9) heats the liquid layer
+    more than the top wall (T~ 0.7) cools the vapour, since conduction scales with rho."""
+    case = I.pool_boiling_3d(n=512)
+    print("pool boiling 512^3, 10000 steps", flush=True)
+    with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"]) as s:
+        t0 = s.reduce()
+        for _ in range(10):
+            s.step(1000)
+        t1 = s.reduce()
+        m = s.moments()
+    del case
+    drift = (t1[0] - t0[0]) / t0[0]
+    print("512^3 pool boiling 10000 steps: mass rel %.2e, energy %.6g -> %.6g" %
+          (drift, t0[4], t1[4]), flush=True)
+    for k in m:
+        assert np.all(np.isfinite(m[k])), k
+    assert abs(drift) < 1e-6
+    assert t1[4] > t0[4]
+    assert m["T"][0].mean() > m["T"][-1].mean()

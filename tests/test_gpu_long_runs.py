@@ -109,3 +109,34 @@ def test_pool_boiling_128_2000_steps_heats_from_the_bottom():
     assert t1[4] > t0[4]
     assert 0.8 * p["T_c"] < T_bottom_plane < p["T_bottom"]
     assert np.isfinite(m["T"]).all()
+
+
+# The 256^3 spinodal at its listed T~ = 0.75 with c_v = 8 p_c (gamma = 4/3).  With c_v = 4 p_c
+# the pressure work cools the vapour out of the EOS domain within about 700 steps, in the oracle
+# (32^3) as on the GPU; the paper does not fix c_v, and with twice the heat capacity the same
+# work cools half as much: the oracle runs 5000 steps of this state at 32^3 and 64^3.
+CV_T075 = 8.0 * I.P_C
+
+
+def test_spinodal_256_at_t075_5000_steps_fp32_and_fp64_agree_statistically():
+    case = I.spinodal_3d(Tr=0.75, params=I.physics(c_v=CV_T075))
+    stats = {}
+    for storage in (4, 8):
+        print("spinodal 256^3 T~ 0.75 c_v 8 p_c %dB, 5000 steps" % storage, flush=True)
+        m = _moments_after(case, 5000, storage)
+        rho, T = m["rho"], m["T"]
+        rv, rl = I.coexistence(0.75)
+        mid = 0.5 * (rv + rl)
+        liq = rho > mid
+        stats[storage] = (liq.mean(), T[liq].mean(), T[~liq].mean(), rho[liq].mean(),
+                          rho[~liq].mean())
+        assert np.isfinite(T).all() and np.isfinite(rho).all()
+        del m, rho, T, liq
+        print("spinodal 256^3 T~ 0.75 %dB, 5000 steps: liquid fraction %.4f, T_liq %.4f, "
+              "T_vap %.4f, rho_liq %.4f, rho_vap %.4f" % ((storage,) + stats[storage]), flush=True)
+    a, b = stats[4], stats[8]
+    assert abs(a[0] - b[0]) < 2e-3
+    for x, y in zip(a[1:], b[1:]):
+        assert abs(x - y) < 2e-3
+    # the pressure work cools the vapour below the liquid (sections 6.2-6.3)
+    assert a[2] < a[1]

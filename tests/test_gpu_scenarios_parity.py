@@ -1,0 +1,118 @@
+"""The paper's experiments (section 6) against the oracle on the GPU path: every scenario input
+of tests/scenarios.py run for a prefix the oracle can follow, element by element, and the two
+experiments whose whole content is a curve the oracle's closed forms give: the coexistence
+densities against the Maxwell construction (Fig. 4b) and the sound speeds against 1/C_V
+(Fig. 8, eq:sspeed)."""
+import numpy as np
+import pytest
+from scipy.optimize import curve_fit
+
+import oracle
+from paper_1705_10045_amd import inputs as I
+from paper_1705_10045_amd import lbm
+from parity import compare, describe
+
+import scenarios as S
+
+pytestmark = pytest.mark.gpu
+
+TOL = {4: 1e-5, 8: 1e-11}
+
+
+@pytest.mark.parametrize("name,build,steps,storage", [
+    ("hot gas 1D at rest, chi 0", lambda: S.hot_gas_1d(), 2000, 8),
+    ("hot gas 1D at u 0.1, chi 0", lambda: S.hot_gas_1d(u=0.1), 2000, 8),
+    ("hot gas 1D, chi 0.01", lambda: S.hot_gas_1d(chi=0.01), 2000, 8),
+    ("hot gas 1D, chi 0.1", lambda: S.hot_gas_1d(chi=0.1), 2000, 8),
+    ("hot gas 1D at u 0.1, FP32", lambda: S.hot_gas_1d(u=0.1), 2000, 4),
+    ("spinodal 1D, work on", lambda: S.spinodal_1d(), 2000, 8),
+    ("spinodal 1D, work off", lambda: S.spinodal_1d(flags=I.ALL_TERMS & ~I.WORK), 2000, 8),
+    ("spinodal 1D, latent 0.02 p_c", lambda: S.spinodal_1d(rhoQ=0.02 * I.P_C), 2000, 8),
+    ("spinodal 2D 500^2", lambda: S.spinodal_2d(), 100, 8),
+    ("spinodal 2D 500^2, FP32", lambda: S.spinodal_2d(), 100, 4),
+    ("moving drop 2D 1000^2", lambda: S.moving_drop_2d(), 100, 8),
+])
+def test_scenario_prefix_against_oracle(name, build, steps, storage):
+    case = build()
+    print("scenario %s: %d steps, %dB" % (name, steps, storage), flush=True)
+    errs, *_ = compare(case, steps, storage)
+    describe("%s %dB, %d steps" % (name, storage, steps), errs)
+    assert max(errs.values()) < TOL[storage]
+
+
+# Fig. 4b: bulk densities of a flat liquid layer at steady state (barotropic, T fixed) against
+# the Maxwell construction.  Vapour above it by the tabulated margin (shrinking towards T_c, as
+# the figure shows), liquid within 0.1%; the GPU's densities equal the oracle's.
+COEX_VAPOUR_MARGIN = {0.6: 0.06, 0.7: 0.03, 0.8: 0.015, 0.85: 0.01, 0.9: 0.005, 0.947: 0.003}
+
+
+def test_coexistence_curve_against_maxwell():
+    n, steps = 128, 12000
+    shape = (1, 1, n)
+    dev = {}
+    for Tr, margin in COEX_VAPOUR_MARGIN.items():
+        rv, rl, _ = oracle.maxwell(Tr)
+        p = I.physics(flags=I.BAROTROPIC | I.PSEUDOFORCE, T0_baro=Tr)
+        rho = I.two_phase_smooth(I.slab_distance(shape, 64, 0), rl, rv)
+        case = dict(Q=9, params=p, rho0=rho, u0=np.zeros((3,) + shape), T0=np.full(shape, Tr))
+        with lbm.Sim(9, p, rho, case["u0"], case["T0"], storage_bytes=8) as s:
+            s.step(steps)
+            g = s.moments()["rho"].ravel()
+        o = oracle.Sim(9, p, rho, case["u0"], case["T0"])
+        o.step(steps)
+        r = o.moments()["rho"].ravel()
+        o.close()
+        assert np.abs(g - r).max() < 1e-10 * r.max()
+        liq, vap = g[n // 2] / rl - 1, g[0] / rv - 1
+        dev[Tr] = vap
+        print("coexistence T~ %.3f: liquid %+.2e, vapour %+.3e of Maxwell (%.6f, %.6f)"
+              % (Tr, liq, vap, rl, rv), flush=True)
+        assert abs(liq) < 1e-3
+        assert 0 < vap < margin
+    v = [dev[t] for t in sorted(dev)]
+    assert all(a > b for a, b in zip(v, v[1:]))
+
+
+def _sound_speed_sq_gpu(flags, c_v, tau_E, L=128, rho0=0.01, T0=0.8, steps=1500):
+    shape = (1, 1, L)
+    x = np.arange(L)
+    k = 2 * np.pi / L
+    p = I.physics(flags=flags, c_v=c_v, chi=0.0, tau_E=tau_E)
+    rho = (rho0 * (1 + 1e-3 * np.cos(k * x))).reshape(shape)
+    a = np.empty(steps)
+    with lbm.Sim(9, p, rho, np.zeros((3,) + shape), np.full(shape, T0), storage_bytes=8) as s:
+        for t in range(steps):
+            a[t] = s.moments()["rho"].ravel() @ np.cos(k * x) * 2 / L
+            s.step(1)
+    t = np.arange(steps)
+    model = lambda t, A, w, ph, G, B, C: A * np.cos(w * t + ph) * np.exp(-G * t) + B + C * t
+    popt, _ = curve_fit(model, t, a, p0=[a[0], 0.25 * k, 0, 1e-4, 0, 0], maxfev=20000)
+    w, G = popt[1], popt[3]
+    return (w * w + G * G) / k ** 2
+
+
+def test_sound_speed_against_heat_capacity():
+    """Fig. 8, eq:sspeed: a standing wave in the vapour at rho~ = 0.01, T~ = 0.8.  Without
+    pressure work the isothermal c_T^2 = (p_c/rho_c) dp~/drho~ holds whatever c_v; with it the
+    adiabatic c_S^2 = c_T^2 + (dp/dT)_rho p / (rho^2 c_v), linear in 1/c_v, close to the paper's
+    24 gamma T~/(3 - rho~)^2 - 6 rho~ (gamma = 1 + (8/3) p_c/(rho_c T_c c_v))."""
+    pc, rho0, T0 = I.P_C, 0.01, 0.8
+    cT2 = pc * (24 * T0 / (3 - rho0) ** 2 - 6 * rho0)
+    dpdT = pc * 8 * rho0 / (3 - rho0)
+    pr = pc * (8 * rho0 * T0 / (3 - rho0) - 3 * rho0 ** 2)
+    cvs = (0.5 * pc, 2 * pc, 8 * pc)
+    ms = []
+    for cv in cvs:
+        c2T = _sound_speed_sq_gpu(I.PSEUDOFORCE, cv, 1.0)
+        c2S = _sound_speed_sq_gpu(I.PSEUDOFORCE | I.WORK, cv, 0.53)
+        gamma = 1 + (8.0 / 3.0) * pc / cv
+        print("sound speed c_v %.3f p_c: c_T^2/closed %.5f, c_S^2/model %.5f, c_S^2/eq:sspeed %.5f"
+              % (cv / pc, c2T / cT2, c2S / (cT2 + dpdT * pr / (rho0 ** 2 * cv)),
+                 c2S / (pc * (24 * gamma * T0 / (3 - rho0) ** 2 - 6 * rho0))), flush=True)
+        assert c2T == pytest.approx(cT2, rel=0.01)
+        assert c2S == pytest.approx(cT2 + dpdT * pr / (rho0 ** 2 * cv), rel=0.01)
+        assert c2S == pytest.approx(pc * (24 * gamma * T0 / (3 - rho0) ** 2 - 6 * rho0), rel=0.015)
+        ms.append(c2S)
+    inv = 1.0 / np.array(cvs)
+    fit = np.polyfit(inv, ms, 1)
+    assert np.abs(np.polyval(fit, inv) - ms).max() < 2e-3 * max(ms)

@@ -126,3 +126,43 @@ def test_continuous_arrivals_complete():
     assert rep["peak_in_flight"] <= 8
     print("serving: p50 %.3fs p99 %.3fs %.0f MLUPS" % (rep["p50_s"], rep["p99_s"],
                                                        rep["aggregate_mlups"]), flush=True)
+
+
+def test_admissions_and_collections_overlap_replay_in_flight():
+    """With lbm_pool_run_async a replay stays in flight while requests are admitted (upload and
+    initial state on the pool's second stream) and finished ones are collected.  Each result must
+    still equal its single simulation bit for bit, whichever replay it joined."""
+    reqs = [_req(20 + i, e, s, k, t) for i, (e, s, k, t) in enumerate(
+        [(32, 35, "droplet", 0.8), (48, 23, "slab", 0.85), (32, 61, "slab", 0.75),
+         (64, 17, "droplet", 0.9), (48, 44, "droplet", 0.82), (32, 12, "slab", 0.88)])]
+    results = {}
+    with lbm.Pool(2 * GIB, max_slots=3, steps_per_run=5) as pool:
+        waiting = list(reqs)
+        inflight = {}
+        replays = 0
+        while waiting or inflight:
+            # admit one request per replay at most, so admissions land while a replay runs
+            if waiting and pool.stats()["free_slots"] > 0:
+                r = waiting.pop(0)
+                f = I.request_fields(r)
+                t = pool.submit(f["params"], f["rho0"], f["u0"], f["T0"], r["steps"])
+                assert t is not None
+                inflight[t] = r
+            pool.run_async()
+            replays += 1
+            assert replays < 200
+            for t in list(inflight):
+                done, st = pool.poll(t)
+                if done:
+                    res, st = pool.collect(t)
+                    assert st == lbm.LBM_OK
+                    results[inflight.pop(t)["id"]] = res
+        pool.run()   # nothing active: returns at once
+    assert len(results) == len(reqs)
+    for r in reqs:
+        f = I.request_fields(r)
+        with lbm.Sim(19, f["params"], f["rho0"], f["u0"], f["T0"], storage_bytes=4) as s:
+            s.step(r["steps"])
+            single = s.moments()
+        for k in single:
+            assert np.array_equal(results[r["id"]][k], single[k]), (r["id"], k)
