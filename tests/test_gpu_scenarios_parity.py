@@ -26,7 +26,9 @@ TOL = {4: 1e-5, 8: 1e-11}
     ("hot gas 1D, chi 0.1", lambda: S.hot_gas_1d(chi=0.1), 2000, 8),
     ("hot gas 1D at u 0.1, FP32", lambda: S.hot_gas_1d(u=0.1), 2000, 4),
     ("spinodal 1D, work on", lambda: S.spinodal_1d(), 2000, 8),
-    ("spinodal 1D, work off", lambda: S.spinodal_1d(flags=I.ALL_TERMS & ~I.WORK), 2000, 8),
+    # without pressure work the decay is chaotic enough that the oracle against itself with the
+    # initial density moved by one ulp differs by 5e-12 at step 500 and 1e-10 at step 2000
+    ("spinodal 1D, work off", lambda: S.spinodal_1d(flags=I.ALL_TERMS & ~I.WORK), 300, 8),
     ("spinodal 1D, latent 0.02 p_c", lambda: S.spinodal_1d(rhoQ=0.02 * I.P_C), 2000, 8),
     ("spinodal 2D 500^2", lambda: S.spinodal_2d(), 100, 8),
     ("spinodal 2D 500^2, FP32", lambda: S.spinodal_2d(), 100, 4),
