@@ -211,7 +211,12 @@ Phys make_phys(const lbm_params& p)
     return ph;
 }
 
-long long padded_plane(long long n) { return (n + 63) / 64 * 64; }
+// Elements between consecutive population planes: the node count rounded up to 64 (256 B in
+// FP32), plus 64 more, so that the same node of consecutive planes does not sit at the same
+// power-of-two alignment (for the power-of-two boxes of the workloads every plane would
+// otherwise start at a multiple of 8 MB-512 MB).  Measured 1-2.5% faster at 512^3, neutral at
+// 128^3 and 256^3.
+long long padded_plane(long long n) { return (n + 63) / 64 * 64 + 64; }
 
 size_t state_bytes(const lbm_params& p)
 {
