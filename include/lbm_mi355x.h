@@ -138,7 +138,8 @@ typedef struct lbm_sim lbm_sim;
  * 1/(2d + 1) with conduction and a held wall (its face is half a cell away), a non-finite
  * gravity, a collision other than LBM_COLLISION_BGK / _MRT or an MRT rate outside (0, 2), a
  * box whose population
- * plane (nx*ny*nz values) would exceed 4 GB (beyond any state that fits in HBM), chi >= 0.5/d with
+ * plane (nx*ny*nz values, x rows padded to whole 128-byte lines) would exceed 4 GB (beyond any
+ * state that fits in HBM), chi >= 0.5/d with
  * conduction on (d = number of axes with extent > 1; section 6.1), a non-positive or
  * non-finite field, rho0/rho_c >= 3, Phi^2 = rho theta - p <= 0 at any node (section 3), and
  * an initial field violating (dp/drho)_T <= (h/dt)^2 + theta (section 3). */
@@ -191,6 +192,18 @@ lbm_status lbm_moments_device_noalloc(lbm_sim* sim, double* rho, double* u_star,
  * that of the populations before they bounce back, and the walls exchange energy and
  * momentum. */
 lbm_status lbm_reduce(lbm_sim* sim, double out[5]);
+
+/* lbm_step followed by lbm_reduce, with the totals formed inside the last of the nsteps (>= 1)
+ * steps: its collision sums, in FP64, the post-collision populations it stores (section 2,
+ * eq:edm; the same quantities as lbm_reduce, out[0..4] as there, equal to them up to the order
+ * of the FP64 sums), so the state is not read a second time.  The fields are bitwise those of
+ * lbm_step.  The launch variants that have no such fused form (lbm_set_launch variants other
+ * than the defaults) run the step and then the separate reduction.  The first call, and any
+ * call after lbm_set_launch raised the workgroup count, allocates a device array of 5 doubles
+ * per workgroup that the simulation keeps until lbm_free.  Synchronises; returns
+ * LBM_EUNSTABLE like lbm_step (out is then not meaningful) and LBM_EINVAL for nsteps < 1 or
+ * a NULL out. */
+lbm_status lbm_step_reduce(lbm_sim* sim, int nsteps, double out[5]);
 
 /* Number of time steps taken since lbm_init (or restored by lbm_restore). */
 long long lbm_step_count(const lbm_sim* sim);
@@ -278,6 +291,13 @@ lbm_status lbm_pool_poll(lbm_pool* pool, long long ticket, int* done, lbm_status
 /* Copy the final fields of a finished request (as lbm_moments) and release its slot. */
 lbm_status lbm_pool_collect(lbm_pool* pool, long long ticket, double* rho, double* u_star,
                             double* E, double* T);
+
+/* Totals of a finished request that has not been collected yet, as lbm_reduce gives them
+ * (mass, momentum x/y/z, internal energy; FP64, fixed order): initial[] of the state right
+ * after admission, final_[] of its last state.  Either may be NULL.  LBM_EBUSY if the ticket
+ * has not finished, LBM_EINVAL for an unknown ticket.  Synchronises the pool's second stream
+ * only (a replay in flight continues). */
+lbm_status lbm_pool_totals(lbm_pool* pool, long long ticket, double initial[5], double final_[5]);
 
 /* Counters: out[0] active slots, out[1] bytes in use, out[2] budget, out[3] free slots. */
 lbm_status lbm_pool_stats(const lbm_pool* pool, long long out[4]);

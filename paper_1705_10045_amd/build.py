@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "liblbm_mi355x.so")
-SOURCES = ["api.hip", "kernels.hip", "serve.hip", "noalloc.hip"]
+SOURCES = ["api.hip", "kernels.hip", "kernels_red.hip", "serve.hip", "noalloc.hip"]
 # the bandwidth-ceiling probe of the benchmark, a library of its own (not part of the ABI)
 PROBE_SOURCES = ["ceiling.hip"]
 PROBE_LIB = os.path.join(OUT_DIR, "libceiling.so")

@@ -218,10 +218,15 @@ Phys make_phys(const lbm_params& p)
 // 128^3 and 256^3.
 long long padded_plane(long long n) { return (n + 63) / 64 * 64 + 64; }
 
+// Elements of one population plane's rows (x rows padded to the row pitch).
+long long plane_elements(const lbm_params& p)
+{
+    return (long long)row_pitch(p.nx, p.storage_bytes) * p.ny * p.nz;
+}
+
 size_t state_bytes(const lbm_params& p)
 {
-    const long long n = (long long)p.nx * p.ny * p.nz;
-    return (size_t)2 * p.lattice * padded_plane(n) * p.storage_bytes;
+    return (size_t)2 * p.lattice * padded_plane(plane_elements(p)) * p.storage_bytes;
 }
 
 lbm_status validate_params(const lbm_params* p)
@@ -298,9 +303,9 @@ lbm_status validate_params(const lbm_params* p)
             }
     }
     // the step addresses nodes within one population plane with 32-bit byte offsets
-    const long long n = (long long)p->nx * p->ny * p->nz;
+    const long long n = plane_elements(*p);
     if ((unsigned long long)padded_plane(n) * (unsigned long long)p->storage_bytes >= (1ull << 32)) {
-        set_error("one population plane of %lld nodes exceeds 4 GB", n);
+        set_error("one population plane of %lld elements exceeds 4 GB", n);
         return LBM_EINVAL;
     }
     if ((p->flags & LBM_LATENT) && !maxwell_table().ok) { set_error("Maxwell table construction failed"); return LBM_EDEVICE; }
@@ -353,6 +358,7 @@ void choose_geometry(lbm_sim* s, int chunk_request)
     step_tile(p.lattice, p.storage_bytes, s->variant, tx, ty, per_cu);
     StepGeom& g = s->geom;
     g.nx = p.nx; g.ny = p.ny; g.nz = p.nz;
+    g.pitch = row_pitch(p.nx, p.storage_bytes);
     g.plane = s->plane;
     g.ntx = (p.nx + tx - 1) / tx;
     g.nty = (p.ny + ty - 1) / ty;
@@ -361,16 +367,28 @@ void choose_geometry(lbm_sim* s, int chunk_request)
     // kernel gives each round a contiguous band of tiles
     g.resident = s->cus * per_cu;
     if (p.lattice == 19) {
-        // about as many workgroups as the compute units hold at once (one round), with the
-        // longest z chunks that allows: each chunk runs the moment stage on 4 planes outside it
-        // (2 on each side), so longer chunks waste less (chunks of at least 4 planes)
+        // z chunks.  Each chunk runs the moment stage on 4 planes outside it (2 on each side),
+        // and the launch runs in rounds of `target` workgroups (later ones start as earlier
+        // ones retire), so a step takes about ceil(workgroups / target) x (chunk + 4) plane
+        // times of one workgroup.  The chunk count minimising that is taken (the fewest
+        // chunks among equals; chunks of at least 4 planes): a box whose columns do not fill
+        // whole rounds gets more, shorter chunks (288^3: 162 columns, 3 chunks, 486
+        // workgroups in two nearly full rounds, instead of 324 in one full and one quarter
+        // round), and powers of two keep one round of long chunks.
         const long long cols = (long long)g.ntx * g.nty;
         const long long target = (long long)s->cus * per_cu;
-        long long want = (target + cols - 1) / cols;
         const long long maxc = p.nz / 4 > 0 ? p.nz / 4 : 1;
-        if (want > maxc) want = maxc;
-        if (want < 1) want = 1;
-        chunk = (int)((p.nz + want - 1) / want);
+        long long best_cost = -1;
+        for (long long nc = 1; nc <= maxc; ++nc) {
+            const long long c = (p.nz + nc - 1) / nc;
+            const long long chunks = (p.nz + c - 1) / c;
+            const long long rounds = (cols * chunks + target - 1) / target;
+            const long long cost = rounds * (c + 4);
+            if (best_cost < 0 || cost < best_cost) {
+                best_cost = cost;
+                chunk = (int)c;
+            }
+        }
         if (chunk_request > 0) chunk = chunk_request < p.nz ? chunk_request : p.nz;
     }
     g.chunk = chunk;
@@ -486,7 +504,7 @@ lbm_status lbm_init(const lbm_params* params, const double* rho0, const double* 
     s->p = *params;
     s->phys = make_phys(*params);
     s->n = (long long)params->nx * params->ny * params->nz;
-    s->plane = padded_plane(s->n);
+    s->plane = padded_plane(plane_elements(s->p));
     if (hipError_t e = hipGetDevice(&s->device); e != hipSuccess) {
         delete s;
         return hip_fail(e, "hipGetDevice");
@@ -504,10 +522,6 @@ lbm_status lbm_init(const lbm_params* params, const double* rho0, const double* 
         if (e != hipSuccess) { delete s; return hip_fail(e, "hipStreamCreate"); }
         s->own_stream = true;
     }
-    // D2Q9 FP32 boxes of 2^19 nodes and more start on 64x8 tiles (512 threads): 5-12% faster
-    // than 32x8 at 1000^2, equal at 500^2, slower on small boxes (fewer workgroups)
-    if (s->p.lattice == 9 && s->p.storage_bytes == 4 && (long long)s->p.nx * s->p.ny >= (1LL << 19))
-        s->variant = 2;
     choose_geometry(s, 0);
     const size_t bytes = state_bytes(s->p);
     hipError_t e = hipMalloc(&s->buf[0], bytes);
@@ -535,6 +549,7 @@ lbm_status lbm_init(const lbm_params* params, const double* rho0, const double* 
     }
     s->aux.eos_p = s->d_eos_p;
     s->aux.eos_coex = s->d_eos_coex;
+    s->aux.partials = nullptr;   // set by the steps that form the totals
     // the caller's table pointers are not kept
     s->p.eos_p = nullptr;
     s->p.eos_coex = nullptr;
@@ -547,7 +562,7 @@ lbm_status lbm_init(const lbm_params* params, const double* rho0, const double* 
     if (e == hipSuccess) e = hipMemcpyAsync(d_fields + 4 * s->n, T0, sizeof(double) * s->n, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
         e = launch_init(s->p.lattice, s->p.storage_bytes, s->buf[0], d_fields, d_fields + s->n, d_fields + 4 * s->n,
-                        s->p.nx, s->p.ny, s->p.nz, s->plane, s->p.c_v, s->p.walls, s->stream);
+                        s->p.nx, s->p.ny, s->p.nz, s->geom.pitch, s->plane, s->p.c_v, s->p.walls, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     (void)hipFree(d_fields);
     if (e != hipSuccess) { lbm_status r = hip_fail(e, "initial state"); lbm_free(s); return r; }
@@ -621,8 +636,8 @@ lbm_status lbm_moments_device(lbm_sim* s, double* rho, double* u_star, double* E
     lbm_status st = ensure_scratch(s);
     if (st != LBM_OK) return st;
     hipError_t e = launch_moments(s->p.lattice, s->p.storage_bytes, s->buf[s->cur], s->d_scratch, s->p.nx,
-                                  s->p.ny, s->p.nz, s->plane, s->phys, s->aux.eos_p, s->d_err, rho, u_star, E,
-                                  T, s->stream);
+                                  s->p.ny, s->p.nz, s->geom.pitch, s->plane, s->phys, s->aux.eos_p, s->d_err, rho,
+                                  u_star, E, T, s->stream);
     if (e != hipSuccess) return hip_fail(e, "moments launch");
     return LBM_OK;
 }
@@ -638,7 +653,7 @@ lbm_status lbm_moments(lbm_sim* s, double* rho, double* u_star, double* E, doubl
     double* scr = s->d_scratch;
     double* d_us = scr + 7 * n;
     hipError_t e = launch_moments(s->p.lattice, s->p.storage_bytes, s->buf[s->cur], scr, s->p.nx, s->p.ny,
-                                  s->p.nz, s->plane, s->phys, s->aux.eos_p, s->d_err, nullptr,
+                                  s->p.nz, s->geom.pitch, s->plane, s->phys, s->aux.eos_p, s->d_err, nullptr,
                                   u_star ? d_us : nullptr, nullptr, nullptr, s->stream);
     if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, scr, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess && u_star) e = hipMemcpyAsync(u_star, d_us, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s->stream);
@@ -655,17 +670,65 @@ lbm_status lbm_reduce(lbm_sim* s, double out[5])
     if (!s || !out) { set_error("NULL argument"); return LBM_EINVAL; }
     if (lbm_status sd = use_device(s->device); sd != LBM_OK) return sd;
     double* d_out = s->d_partials + 5 * s->red_blocks;
-    hipError_t e = launch_reduce(s->p.lattice, s->p.storage_bytes, s->buf[s->cur], s->n, s->plane, s->d_partials,
-                                 s->red_blocks, d_out, s->stream);
+    // the padding of the rows is zero (cleared at init, never written by the step)
+    hipError_t e = launch_reduce(s->p.lattice, s->p.storage_bytes, s->buf[s->cur], plane_elements(s->p), s->plane,
+                                 s->d_partials, s->red_blocks, d_out, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, sizeof(double) * 5, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return hip_fail(e, "reduction");
     return LBM_OK;
 }
 
+lbm_status lbm_step_reduce(lbm_sim* s, int nsteps, double out[5])
+{
+    clear_error();
+    if (!s || !out || nsteps < 1) {
+        set_error("bad simulation handle, NULL output or step count below 1");
+        return LBM_EINVAL;
+    }
+    if (lbm_status sd = use_device(s->device); sd != LBM_OK) return sd;
+    lbm_status st = enqueue_steps(s, nsteps - 1);
+    if (st != LBM_OK) return st;
+    // the last step's partial totals (5 per workgroup) and the totals, grown on demand
+    const long long wg = step_workgroups(s->geom);
+    if (5 * wg + 8 > s->step_partials_len) {
+        if (s->d_step_partials) {
+            hipError_t e = hipFree(s->d_step_partials);
+            s->d_step_partials = nullptr;
+            s->step_partials_len = 0;
+            if (e != hipSuccess) return hip_fail(e, "hipFree(step partials)");
+        }
+        hipError_t e = hipMalloc((void**)&s->d_step_partials, sizeof(double) * (5 * wg + 8));
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(step partials)");
+        s->step_partials_len = 5 * wg + 8;
+    }
+    double* d_out = s->d_step_partials + 5 * wg;
+    StepAux aux = s->aux;
+    aux.partials = s->d_step_partials;
+    hipError_t e = launch_step_totals(s->p.lattice, s->p.storage_bytes, s->variant, s->buf[s->cur],
+                                      s->buf[1 - s->cur], s->geom, s->phys, aux, d_out, s->stream);
+    if (e == hipErrorNotSupported) {
+        // a launch variant without the fused form: the plain step, then the separate reduction
+        st = enqueue_steps(s, 1);
+        if (st != LBM_OK) return st;
+        e = launch_reduce(s->p.lattice, s->p.storage_bytes, s->buf[s->cur], plane_elements(s->p), s->plane,
+                          s->d_partials, s->red_blocks, d_out, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "reduction");
+    } else if (e != hipSuccess) {
+        return hip_fail(e, "step launch");
+    } else {
+        s->cur ^= 1;
+        s->step += 1;
+    }
+    e = hipMemcpyAsync(out, d_out, sizeof(double) * 5, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "reading the totals");
+    return read_error_word(s);
+}
+
 struct CheckpointHeader {
     char magic[8];
-    int lattice, nx, ny, nz, storage_bytes, pad;
+    int lattice, nx, ny, nz, storage_bytes, pitch;   // pitch: x row pitch of the layout, in elements
     long long step;
     long long bytes;
 };
@@ -681,9 +744,9 @@ lbm_status lbm_checkpoint(lbm_sim* s, void* host_buf, size_t cap, size_t* used)
     if (lbm_status sd = use_device(s->device); sd != LBM_OK) return sd;
     CheckpointHeader h;
     memset(&h, 0, sizeof(h));
-    memcpy(h.magic, "LBMCKPT1", 8);
+    memcpy(h.magic, "LBMCKPT2", 8);
     h.lattice = s->p.lattice; h.nx = s->p.nx; h.ny = s->p.ny; h.nz = s->p.nz;
-    h.storage_bytes = s->p.storage_bytes; h.step = s->step; h.bytes = (long long)bytes;
+    h.storage_bytes = s->p.storage_bytes; h.pitch = s->geom.pitch; h.step = s->step; h.bytes = (long long)bytes;
     memcpy(host_buf, &h, sizeof(h));
     hipError_t e = hipMemcpyAsync((char*)host_buf + sizeof(h), s->buf[s->cur], bytes, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -699,8 +762,9 @@ lbm_status lbm_restore(lbm_sim* s, const void* host_buf, size_t len)
     if (len < sizeof(h)) { set_error("checkpoint too short"); return LBM_EINVAL; }
     memcpy(&h, host_buf, sizeof(h));
     const size_t bytes = state_bytes(s->p);
-    if (memcmp(h.magic, "LBMCKPT1", 8) != 0 || h.lattice != s->p.lattice || h.nx != s->p.nx || h.ny != s->p.ny ||
-        h.nz != s->p.nz || h.storage_bytes != s->p.storage_bytes || h.bytes != (long long)bytes ||
+    if (memcmp(h.magic, "LBMCKPT2", 8) != 0 || h.lattice != s->p.lattice || h.nx != s->p.nx || h.ny != s->p.ny ||
+        h.nz != s->p.nz || h.storage_bytes != s->p.storage_bytes || h.pitch != s->geom.pitch ||
+        h.bytes != (long long)bytes ||
         len < sizeof(h) + bytes) {
         set_error("checkpoint does not match this simulation's lattice, shape or storage");
         return LBM_EINVAL;
@@ -724,6 +788,7 @@ lbm_status lbm_free(lbm_sim* s)
     if (s->buf[1]) (void)hipFree(s->buf[1]);
     if (s->d_err) (void)hipFree(s->d_err);
     if (s->d_partials) (void)hipFree(s->d_partials);
+    if (s->d_step_partials) (void)hipFree(s->d_step_partials);
     if (s->d_table) (void)hipFree(s->d_table);
     if (s->d_scratch) (void)hipFree(s->d_scratch);
     if (s->d_eos_p) (void)hipFree(s->d_eos_p);

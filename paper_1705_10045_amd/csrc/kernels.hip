@@ -4,9 +4,11 @@
 #include "kernels.hpp"
 #include "lattice.hpp"
 #include "physics.hpp"
-#include "step_kernel.hpp"
+#include "step_launch.hpp"
 
 namespace lbm {
+
+using step_launch::launch_step_t;
 
 namespace {
 
@@ -23,12 +25,18 @@ __device__ __forceinline__ long long node_index(int x, int y, int z, int nx, int
     return wrap_index(x, nx) + (long long)nx * (wrap_index(y, ny) + (long long)ny * wrap_index(z, nz));
 }
 
+// Element of node (x, y, z) (periodic wrap) in a population plane whose rows have the pitch.
+__device__ __forceinline__ long long buf_index(int x, int y, int z, int nx, int ny, int nz, int pitch)
+{
+    return wrap_index(x, nx) + (long long)pitch * (wrap_index(y, ny) + (long long)ny * wrap_index(z, nz));
+}
+
 // Equilibrium initial state N_k = rho0 P_k(u0), g_k = rho0 c_v T0 P_k(u0) (eq:feq, section 4),
 // stored in pull form: node y keeps, for direction k, the value belonging to node y + c_k.
 template <int Q, class S>
 __global__ void k_init(S* __restrict__ buf, const double* __restrict__ rho0,
                        const double* __restrict__ u0, const double* __restrict__ T0, int nx,
-                       int ny, int nz, long long plane, double c_v, int walls)
+                       int ny, int nz, int pitch, long long plane, double c_v, int walls)
 {
     using L = Lattice<Q>;
     const long long n = (long long)nx * ny * nz;
@@ -36,6 +44,7 @@ __global__ void k_init(S* __restrict__ buf, const double* __restrict__ rho0,
     if (i >= n) return;
     int x, y, z;
     node_xyz(i, nx, ny, x, y, z);
+    const long long b = buf_index(x, y, z, nx, ny, nz, pitch);
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
         // population k stored at node i is pulled by node i + c_k; toward a wall, it is pulled
@@ -51,16 +60,16 @@ __global__ void k_init(S* __restrict__ buf, const double* __restrict__ rho0,
         const double E = rho * c_v * T0[j];
         const double cu = L::cx[kd] * ux + L::cy[kd] * uy + L::cz[kd] * uz;
         const double P = eq_poly(weight<Q>(kd), cu, ux * ux + uy * uy + uz * uz);
-        buf[(long long)k * plane + i] = S(rho * P);
-        buf[(long long)(Q + k) * plane + i] = S(E * P);
+        buf[(long long)k * plane + b] = S(rho * P);
+        buf[(long long)(Q + k) * plane + b] = S(E * P);
     }
 }
 
 // Moments of the current state in FP64: scratch = [rho | jx | jy | jz | E | T | Phi].
 template <int Q, class S>
 __global__ void k_moments_a(const S* __restrict__ buf, double* __restrict__ scr, int nx, int ny,
-                            int nz, long long plane, Phys ph, const double* __restrict__ eos_p,
-                            int* err)
+                            int nz, int pitch, long long plane, Phys ph,
+                            const double* __restrict__ eos_p, int* err)
 {
     using L = Lattice<Q>;
     const long long n = (long long)nx * ny * nz;
@@ -71,11 +80,11 @@ __global__ void k_moments_a(const S* __restrict__ buf, double* __restrict__ scr,
     double rho = 0, jx = 0, jy = 0, jz = 0, E = 0;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-        long long j = node_index(x - L::cx[k], y - L::cy[k], z - L::cz[k], nx, ny, nz);
+        long long j = buf_index(x - L::cx[k], y - L::cy[k], z - L::cz[k], nx, ny, nz, pitch);
         int pk = k;
         if (ph.walls && (z - L::cz[k] < 0 || z - L::cz[k] >= nz)) {   // bounce-back at a wall
             pk = opposite<Q>(k);
-            j = i;
+            j = buf_index(x, y, z, nx, ny, nz, pitch);
         }
         const double nk = double(buf[(long long)pk * plane + j]);
         rho += nk;
@@ -151,23 +160,33 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 // Block partial sums of mass, momentum and internal energy (FP64): per-thread grid-stride
-// sums, 64-lane wavefront shuffles, then the waves in order.
+// sums over 16-byte vectors of consecutive nodes (a population plane's rows are padded to
+// whole 128-byte lines, so the plane's element count is a multiple of the vector and every
+// plane starts aligned), 64-lane wavefront shuffles, then the waves in order.
 template <int Q, class S>
 __global__ void __launch_bounds__(kReduceThreads)
 k_reduce_partial(const S* __restrict__ buf, long long n, long long plane, double* __restrict__ part)
 {
     using L = Lattice<Q>;
+    constexpr int VEC = 16 / (int)sizeof(S);
+    typedef S V __attribute__((ext_vector_type(VEC)));
+    const long long nv = n / VEC;
     double acc[5] = {0, 0, 0, 0, 0};
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nv;
          i += (long long)gridDim.x * blockDim.x) {
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-            const double nk = double(buf[(long long)k * plane + i]);
-            acc[0] += nk;
-            if (L::cx[k]) acc[1] += L::cx[k] * nk;
-            if (L::cy[k]) acc[2] += L::cy[k] * nk;
-            if (L::cz[k]) acc[3] += L::cz[k] * nk;
-            acc[4] += double(buf[(long long)(Q + k) * plane + i]);
+            const V a = *(const V*)(buf + (long long)k * plane + i * VEC);
+            const V b = *(const V*)(buf + (long long)(Q + k) * plane + i * VEC);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const double nk = double(a[e]);
+                acc[0] += nk;
+                if (L::cx[k]) acc[1] += L::cx[k] * nk;
+                if (L::cy[k]) acc[2] += L::cy[k] * nk;
+                if (L::cz[k]) acc[3] += L::cz[k] * nk;
+                acc[4] += double(b[e]);
+            }
         }
     }
     __shared__ double wsum[kReduceThreads / 64][5];
@@ -185,13 +204,28 @@ k_reduce_partial(const S* __restrict__ buf, long long n, long long plane, double
     }
 }
 
-__global__ void k_reduce_final(const double* __restrict__ part, int nblocks, double* __restrict__ out)
+// Sum of per-block partial totals (5 per block) in a fixed order: thread t adds the entries
+// t, t + 256, ... (independent loads in flight together), then a fixed tree over the threads.
+__global__ void __launch_bounds__(kReduceThreads)
+k_sum_partials(const double* __restrict__ part, long long nblocks, double* __restrict__ out)
 {
-    if (threadIdx.x < 5) {
-        double s = 0;
-        for (int b = 0; b < nblocks; ++b) s += part[b * 5 + threadIdx.x];
-        out[threadIdx.x] = s;
+    __shared__ double red[5][kReduceThreads];
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (long long b = threadIdx.x; b < nblocks; b += kReduceThreads) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) acc[q] += part[b * 5 + q];
     }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
 inline unsigned blocks_for(long long n, int threads)
@@ -199,71 +233,11 @@ inline unsigned blocks_for(long long n, int threads)
     return (unsigned)((n + threads - 1) / threads);
 }
 
-// One buffer resource per buffer needs every byte offset of the two population sets in 32 bits.
-inline bool fits_buffer(const StepGeom& g, int Q, int storage_bytes)
-{
-    return (unsigned long long)g.plane * 2ull * Q * storage_bytes < (1ull << 32);
-}
-
-
-// The periodic instantiation, the one with walls and body force when the parameters ask for
-// them, or the one that also carries the tabulated equation of state.
-template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool STASH, int ADDR,
-          int NMODE>
-hipError_t launch_one(const void* src, void* dst, const StepGeom& g, const Phys& ph,
-                      const StepAux& aux, hipStream_t st)
-{
-    const unsigned nblk = (unsigned)(g.ntx * g.nty * g.nchunks);
-    const bool ext = ph.walls || ph.g[0] != 0.0 || ph.g[1] != 0.0 || ph.g[2] != 0.0;
-    if (ph.eos != 0)
-        hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, NTH, PIPE, ADDR, NMODE, STASH, kExtTable>),
-                           dim3(nblk), dim3(NTH), 0, st, (const S*)src, (S*)dst, g, ph, aux);
-    else if (ext)
-        hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, NTH, PIPE, ADDR, NMODE, STASH, kExtWalls>),
-                           dim3(nblk), dim3(NTH), 0, st, (const S*)src, (S*)dst, g, ph, aux);
-    else
-        hipLaunchKernelGGL((k_step<Q, S, R, TX, TY, NTH, PIPE, ADDR, NMODE, STASH, kExtNone>),
-                           dim3(nblk), dim3(NTH), 0, st, (const S*)src, (S*)dst, g, ph, aux);
-    return hipGetLastError();
-}
-
-// Picks the instantiation for the run-time facts: the address form the state allows, the
-// tau = 1 collision (no re-read of N_k) when 1/tau is exactly 1 with BGK, and the MRT collision
-// (which re-reads N_k, with the load order of tau != 1) when asked for.
-//   - FP32 states under 4 GB: one buffer resource per buffer.  Where the variant has the LDS
-//     stash, the density prefetch stays on for tau = 1 only (re-reading N_k in the collision
-//     leaves no registers for it).
-//   - otherwise (FP64, the GLOBAL variant, states of 4 GB and more) global addressing, with the stash
-//     where the variant asks for it and without the prefetch: at 512^3 the step is bound by
-//     HBM traffic, and the stash saves the collision's second pull of the energy populations
-//     (12.6 ms against 14.4 ms for the prefetch alone); not for FP64 with a collision that
-//     re-reads N_k (it would spill).
-template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, bool STASH = false,
-          bool GLOBAL = false>
-hipError_t launch_step_t(const void* src, void* dst, const StepGeom& g, const Phys& ph,
-                         const StepAux& aux, hipStream_t st)
-{
-    const bool mrt = ph.collision != 0;
-    const bool tau1 = ph.omega == 1.0 && !mrt;
-    if constexpr (sizeof(S) == 4 && !GLOBAL) {
-        if (fits_buffer(g, Q, 4)) {
-            if (tau1) return launch_one<Q, S, R, TX, TY, NTH, PIPE, STASH, kAddrBuf, kTauOne>(src, dst, g, ph, aux, st);
-            if (mrt) return launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, kAddrBuf, kMrt>(src, dst, g, ph, aux, st);
-            return launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, kAddrBuf, kTauAny>(src, dst, g, ph, aux, st);
-        }
-    }
-    constexpr bool kStashAnyTau = STASH && sizeof(S) == 4;
-    if (tau1) return launch_one<Q, S, R, TX, TY, NTH, PIPE && !STASH, STASH, kAddrGlobal, kTauOne>(src, dst, g, ph, aux, st);
-    if (mrt) return launch_one<Q, S, R, TX, TY, NTH, PIPE && !kStashAnyTau, kStashAnyTau, kAddrGlobal, kMrt>(src, dst, g, ph, aux, st);
-    return launch_one<Q, S, R, TX, TY, NTH, PIPE && !kStashAnyTau, kStashAnyTau, kAddrGlobal, kTauAny>(src, dst, g, ph, aux, st);
-}
-
 }  // namespace
 
-// Launch shapes of the fused step.  Variant 0 is the default per (lattice, storage), except
-// for large D2Q9 FP32 boxes (variant 2, chosen at init); the others are selected for tuning.  Tile shape,
-// thread count and the order of the loads do not change the per-node arithmetic, so every
-// variant gives bitwise-identical results.
+// Launch shapes of the fused step.  Variant 0 is the default per (lattice, storage); the
+// others are selected for tuning.  Tile shape, thread count and the order of the loads do not
+// change the per-node arithmetic, so every variant gives bitwise-identical results.
 // `per_cu` is the number of workgroups of the variant resident per compute unit (set by its
 // registers and LDS); the automatic z chunk aims at about 256 * per_cu workgroups.
 // FP32 variant 5 is the default launch with plain global addressing, which states of 4 GB
@@ -355,29 +329,29 @@ hipError_t launch_step(int Q, int storage_bytes, int variant, const void* src, v
 }
 
 hipError_t launch_init(int Q, int storage_bytes, void* buf, const double* rho0, const double* u0,
-                       const double* T0, int nx, int ny, int nz, long long plane, double c_v,
-                       int walls, hipStream_t st)
+                       const double* T0, int nx, int ny, int nz, int pitch, long long plane,
+                       double c_v, int walls, hipStream_t st)
 {
     const long long n = (long long)nx * ny * nz;
     const dim3 grid(blocks_for(n, 256)), block(256);
-    if (Q == 19 && storage_bytes == 4) hipLaunchKernelGGL((k_init<19, float>), grid, block, 0, st, (float*)buf, rho0, u0, T0, nx, ny, nz, plane, c_v, walls);
-    else if (Q == 19 && storage_bytes == 8) hipLaunchKernelGGL((k_init<19, double>), grid, block, 0, st, (double*)buf, rho0, u0, T0, nx, ny, nz, plane, c_v, walls);
-    else if (Q == 9 && storage_bytes == 4) hipLaunchKernelGGL((k_init<9, float>), grid, block, 0, st, (float*)buf, rho0, u0, T0, nx, ny, nz, plane, c_v, 0);
-    else if (Q == 9 && storage_bytes == 8) hipLaunchKernelGGL((k_init<9, double>), grid, block, 0, st, (double*)buf, rho0, u0, T0, nx, ny, nz, plane, c_v, 0);
+    if (Q == 19 && storage_bytes == 4) hipLaunchKernelGGL((k_init<19, float>), grid, block, 0, st, (float*)buf, rho0, u0, T0, nx, ny, nz, pitch, plane, c_v, walls);
+    else if (Q == 19 && storage_bytes == 8) hipLaunchKernelGGL((k_init<19, double>), grid, block, 0, st, (double*)buf, rho0, u0, T0, nx, ny, nz, pitch, plane, c_v, walls);
+    else if (Q == 9 && storage_bytes == 4) hipLaunchKernelGGL((k_init<9, float>), grid, block, 0, st, (float*)buf, rho0, u0, T0, nx, ny, nz, pitch, plane, c_v, 0);
+    else if (Q == 9 && storage_bytes == 8) hipLaunchKernelGGL((k_init<9, double>), grid, block, 0, st, (double*)buf, rho0, u0, T0, nx, ny, nz, pitch, plane, c_v, 0);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 hipError_t launch_moments(int Q, int storage_bytes, const void* buf, double* scratch, int nx, int ny,
-                          int nz, long long plane, const Phys& ph, const double* eos_p, int* err,
-                          double* rho, double* us, double* E, double* T, hipStream_t st)
+                          int nz, int pitch, long long plane, const Phys& ph, const double* eos_p,
+                          int* err, double* rho, double* us, double* E, double* T, hipStream_t st)
 {
     const long long n = (long long)nx * ny * nz;
     const dim3 grid(blocks_for(n, 256)), block(256);
-    if (Q == 19 && storage_bytes == 4) hipLaunchKernelGGL((k_moments_a<19, float>), grid, block, 0, st, (const float*)buf, scratch, nx, ny, nz, plane, ph, eos_p, err);
-    else if (Q == 19 && storage_bytes == 8) hipLaunchKernelGGL((k_moments_a<19, double>), grid, block, 0, st, (const double*)buf, scratch, nx, ny, nz, plane, ph, eos_p, err);
-    else if (Q == 9 && storage_bytes == 4) hipLaunchKernelGGL((k_moments_a<9, float>), grid, block, 0, st, (const float*)buf, scratch, nx, ny, nz, plane, ph, eos_p, err);
-    else if (Q == 9 && storage_bytes == 8) hipLaunchKernelGGL((k_moments_a<9, double>), grid, block, 0, st, (const double*)buf, scratch, nx, ny, nz, plane, ph, eos_p, err);
+    if (Q == 19 && storage_bytes == 4) hipLaunchKernelGGL((k_moments_a<19, float>), grid, block, 0, st, (const float*)buf, scratch, nx, ny, nz, pitch, plane, ph, eos_p, err);
+    else if (Q == 19 && storage_bytes == 8) hipLaunchKernelGGL((k_moments_a<19, double>), grid, block, 0, st, (const double*)buf, scratch, nx, ny, nz, pitch, plane, ph, eos_p, err);
+    else if (Q == 9 && storage_bytes == 4) hipLaunchKernelGGL((k_moments_a<9, float>), grid, block, 0, st, (const float*)buf, scratch, nx, ny, nz, pitch, plane, ph, eos_p, err);
+    else if (Q == 9 && storage_bytes == 8) hipLaunchKernelGGL((k_moments_a<9, double>), grid, block, 0, st, (const double*)buf, scratch, nx, ny, nz, pitch, plane, ph, eos_p, err);
     else return hipErrorInvalidValue;
     if (Q == 19) hipLaunchKernelGGL((k_moments_b<19>), grid, block, 0, st, scratch, nx, ny, nz, ph, rho, us, E, T);
     else hipLaunchKernelGGL((k_moments_b<9>), grid, block, 0, st, scratch, nx, ny, nz, ph, rho, us, E, T);
@@ -399,7 +373,14 @@ hipError_t launch_reduce(int Q, int storage_bytes, const void* buf, long long n,
     else if (Q == 9 && storage_bytes == 4) hipLaunchKernelGGL((k_reduce_partial<9, float>), grid, block, 0, st, (const float*)buf, n, plane, partials);
     else if (Q == 9 && storage_bytes == 8) hipLaunchKernelGGL((k_reduce_partial<9, double>), grid, block, 0, st, (const double*)buf, n, plane, partials);
     else return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, st, partials, nblocks, out);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kReduceThreads), 0, st, (const double*)partials,
+                       (long long)nblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double* partials, long long nblocks, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kReduceThreads), 0, st, partials, nblocks, out);
     return hipGetLastError();
 }
 

@@ -69,8 +69,8 @@ extern "C" lbm_status lbm_moments_device_noalloc(lbm_sim* s, double* rho, double
     // the second kernel reads only scratch elements the first one has written in this call, so
     // what an earlier call left there needs no clearing
     const hipError_t e = launch_moments(s->p.lattice, s->p.storage_bytes, s->buf[s->cur], scr, s->p.nx,
-                                        s->p.ny, s->p.nz, s->plane, s->phys, s->aux.eos_p, s->d_err, rho,
-                                        u_star, E, T, s->stream);
+                                        s->p.ny, s->p.nz, s->geom.pitch, s->plane, s->phys, s->aux.eos_p,
+                                        s->d_err, rho, u_star, E, T, s->stream);
     if (e != hipSuccess) return hip_fail(e, "moments launch");
     return LBM_OK;
 }

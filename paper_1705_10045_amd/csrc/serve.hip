@@ -89,6 +89,7 @@ k_pool_step(const SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ h
         aux.err = errs + lo;
         aux.eos_p = nullptr;
         aux.eos_coex = nullptr;
+        aux.partials = nullptr;
         // each request's own collision: tau = 1 (with the density prefetch) or general; both
         // share the workgroup's LDS
         if (ph.omega == 1.0)
@@ -150,6 +151,8 @@ struct lbm_pool {
     double tab_s0 = 0, tab_inv_ds = 0;
     double* d_staging = nullptr;             // initial fields of a request (5 n doubles)
     double* d_scratch = nullptr;             // moment scratch (10 n doubles)
+    double* d_red = nullptr;                 // reduction partials (kPoolRedBlocks x 5)
+    double* d_totals = nullptr;              // per slot: totals at admission, then at the end
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool dirty = true;
@@ -161,6 +164,17 @@ struct lbm_pool {
 namespace {
 
 const size_t kAlign = 256;
+// blocks of the per-slot reductions (a pool state has at most kPoolMaxEdge^3 nodes)
+const int kPoolRedBlocks = 1024;
+
+// FP64 totals of a slot's populations (as lbm_reduce) into out[0..4], on the side stream
+hipError_t slot_reduce(lbm_pool* p, const SlotDesc& d, const lbm_params& prm, int parity, double* out)
+{
+    const long long n = (long long)prm.nx * prm.ny * prm.nz;
+    int blocks = reduce_blocks(n);
+    if (blocks > kPoolRedBlocks) blocks = kPoolRedBlocks;
+    return launch_reduce(19, 4, d.buf[parity], plane_elements(prm), d.geom.plane, p->d_red, blocks, out, p->side);
+}
 
 bool arena_alloc(lbm_pool* p, size_t bytes, size_t& off)
 {
@@ -201,7 +215,8 @@ StepGeom pool_geometry(const lbm_params& p)
 {
     StepGeom g;
     g.nx = p.nx; g.ny = p.ny; g.nz = p.nz;
-    g.plane = padded_plane((long long)p.nx * p.ny * p.nz);
+    g.pitch = row_pitch(p.nx, 4);
+    g.plane = padded_plane(plane_elements(p));
     g.ntx = (p.nx + kPoolTX - 1) / kPoolTX;
     g.nty = (p.ny + kPoolTY - 1) / kPoolTY;
     g.chunk = kPoolChunk < p.nz ? kPoolChunk : p.nz;
@@ -359,6 +374,8 @@ lbm_status lbm_pool_create(size_t hbm_budget_bytes, int max_slots, int steps_per
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_errs, sizeof(int) * max_slots);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_staging, sizeof(double) * 5 * nmax);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_scratch, sizeof(double) * 10 * nmax);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_red, sizeof(double) * 5 * kPoolRedBlocks);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_totals, sizeof(double) * 10 * max_slots);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_table, sizeof(double) * 2 * kMaxwellPoints);
     if (e != hipSuccess) { lbm_status r = hip_fail(e, "pool allocation"); lbm_pool_destroy(p); return r; }
     p->free_blocks[0] = p->budget;
@@ -442,7 +459,9 @@ lbm_status lbm_pool_submit(lbm_pool* p, const lbm_params* params, const double* 
     if (e == hipSuccess) e = hipMemcpyAsync(p->d_staging + 4 * n, T0, sizeof(double) * n, hipMemcpyHostToDevice, p->side);
     if (e == hipSuccess)
         e = launch_init(19, 4, d.buf[0], p->d_staging, p->d_staging + n, p->d_staging + 4 * n, params->nx,
-                        params->ny, params->nz, d.geom.plane, params->c_v, 0, p->side);
+                        params->ny, params->nz, d.geom.pitch, d.geom.plane, params->c_v, 0, p->side);
+    // the totals of the initial state, kept for lbm_pool_totals
+    if (e == hipSuccess) e = slot_reduce(p, d, *params, 0, p->d_totals + 10 * slot);
     // the staging buffer is reused by the next submission, and the next replay must find the
     // initial state in place: wait for this upload (not for the replay in flight)
     if (e == hipSuccess) e = hipStreamSynchronize(p->side);
@@ -505,8 +524,8 @@ lbm_status lbm_pool_collect(lbm_pool* p, long long ticket, double* rho, double* 
     int* d_err = p->d_errs + s;
     // on the side stream: the slot has finished, so a replay in flight does not advance it
     hipError_t e = launch_moments(19, 4, d.buf[d.parity], scr, ps.params.nx, ps.params.ny, ps.params.nz,
-                                  d.geom.plane, d.phys, nullptr, d_err, nullptr, u_star ? d_us : nullptr,
-                                  nullptr, nullptr, p->side);
+                                  d.geom.pitch, d.geom.plane, d.phys, nullptr, d_err, nullptr,
+                                  u_star ? d_us : nullptr, nullptr, nullptr, p->side);
     if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, scr, sizeof(double) * n, hipMemcpyDeviceToHost, p->side);
     if (e == hipSuccess && u_star) e = hipMemcpyAsync(u_star, d_us, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, p->side);
     if (e == hipSuccess && E) e = hipMemcpyAsync(E, scr + 4 * n, sizeof(double) * n, hipMemcpyDeviceToHost, p->side);
@@ -522,6 +541,31 @@ lbm_status lbm_pool_collect(lbm_pool* p, long long ticket, double* rho, double* 
     p->dirty = true;
     if (result != LBM_OK) set_error("request %lld left the EOS domain", ticket);
     return result;
+}
+
+lbm_status lbm_pool_totals(lbm_pool* p, long long ticket, double initial[5], double final_[5])
+{
+    clear_error();
+    if (!p) { set_error("pool is NULL"); return LBM_EINVAL; }
+    auto it = p->ticket_slot.find(ticket);
+    if (it == p->ticket_slot.end()) { set_error("unknown ticket %lld", ticket); return LBM_EINVAL; }
+    if (p->finished.find(ticket) == p->finished.end()) {
+        set_error("ticket %lld has not finished", ticket);
+        return LBM_EBUSY;
+    }
+    const int s = it->second;
+    const SlotDesc& d = p->table[s];
+    if (lbm_status sd = use_device(p->device); sd != LBM_OK) return sd;
+    double h[10];
+    double* d_tot = p->d_totals + 10 * s;
+    // on the side stream: the slot has finished, so a replay in flight does not advance it
+    hipError_t e = slot_reduce(p, d, p->slots[s].params, d.parity, d_tot + 5);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d_tot, sizeof(h), hipMemcpyDeviceToHost, p->side);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->side);
+    if (e != hipSuccess) return hip_fail(e, "slot totals");
+    if (initial) memcpy(initial, h, sizeof(double) * 5);
+    if (final_) memcpy(final_, h + 5, sizeof(double) * 5);
+    return LBM_OK;
 }
 
 lbm_status lbm_pool_stats(const lbm_pool* p, long long out[4])
@@ -554,6 +598,8 @@ lbm_status lbm_pool_destroy(lbm_pool* p)
     if (p->d_errs) (void)hipFree(p->d_errs);
     if (p->d_staging) (void)hipFree(p->d_staging);
     if (p->d_scratch) (void)hipFree(p->d_scratch);
+    if (p->d_red) (void)hipFree(p->d_red);
+    if (p->d_totals) (void)hipFree(p->d_totals);
     if (p->d_table) (void)hipFree(p->d_table);
     if (p->h_up) (void)hipHostFree(p->h_up);
     if (p->h_rb) (void)hipHostFree(p->h_rb);

@@ -22,7 +22,9 @@ struct lbm_sim {
     long long step = 0;
     int* d_err = nullptr;
     double* d_table = nullptr;
-    double* d_partials = nullptr;
+    double* d_partials = nullptr;        // partial sums of lbm_reduce
+    double* d_step_partials = nullptr;   // per-workgroup totals of lbm_step_reduce's last step
+    long long step_partials_len = 0;     // doubles held by d_step_partials
     double* d_scratch = nullptr;         // moment scratch (7n doubles), allocated on first use
     double* d_eos_p = nullptr;           // tabulated EOS: reduced pressures and band per row
     double* d_eos_coex = nullptr;
@@ -40,6 +42,7 @@ lbm_status use_device(int device);
 bool host_band_limits(double Tr, double& rv, double& rl);
 Phys make_phys(const lbm_params& p);
 long long padded_plane(long long n);
+long long plane_elements(const lbm_params& p);
 size_t state_bytes(const lbm_params& p);
 lbm_status validate_params(const lbm_params* p);
 lbm_status validate_fields(const lbm_params& p, const double* rho0, const double* u0, const double* T0);

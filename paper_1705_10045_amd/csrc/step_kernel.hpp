@@ -1,8 +1,8 @@
 // Fused single-sweep time step of the thermal multiphase LBM (one launch per step).
 //
-// Storage: structure of arrays, population k of set s (0 = N, 1 = g) at node i is
-// buf[(s*Q + k)*plane + i], i = x + nx*(y + ny*z).  Two buffers: a step reads `src` and
-// writes `dst`.  Pull scheme: dst holds post-collision populations at the node where they were
+// Storage: structure of arrays, population k of set s (0 = N, 1 = g) at node (x, y, z) is
+// buf[(s*Q + k)*plane + i], i = x + pitch*(y + ny*z), with x rows padded to the pitch.  Two
+// buffers: a step reads `src` and writes `dst`.  Pull scheme: dst holds post-collision populations at the node where they were
 // computed, so the state at time t is N_k(x, t) = src[k][x - c_k].
 //
 // Dependencies of one node update (sections 3-5): the force at x needs Phi on the 1-ring, the
@@ -239,12 +239,19 @@ struct TileLds {
 // plane in registers until its collision has read the older plane of the same ring slot, then
 // moves it there).  With the stash, the prefetch covers the density populations only (the
 // energy pulls already occupy registers until the collision).
+//
+// RED: the step also forms the FP64 totals of the state it writes (mass, momentum, internal
+// energy: what a reduction over the written buffer gives).  Each node sums its stored values
+// in FP64 (mass and energy from the collision's own sums of the moving populations), the
+// collision wavefronts sum their nodes by a butterfly of shuffles per plane and add that into
+// their LDS entry (red_lds: 5 per wavefront), and the workgroup writes the sum of its
+// wavefronts' entries to aux.partials[5 lb ...].  The fields are the same as without it.
 template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, int ADDR, int NMODE,
-          bool STASH, int EXT>
+          bool STASH, int EXT, bool RED = false>
 __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
                                           const S* __restrict__ src, S* __restrict__ dst,
                                           const StepGeom& g, const Phys& ph, const StepAux& aux,
-                                          const int lb)
+                                          const int lb, double* red_lds = nullptr)
 {
     PopIO<S, ADDR> io(src, dst, g.plane, 2 * Q);
     using L = Lattice<Q>;
@@ -288,7 +295,12 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
     const int tiz = lb / (g.ntx * g.nty);
     const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * g.chunk;
     const int z1 = min(z0 + g.chunk, g.nz);
-    const int nxy = g.nx * g.ny;
+    const int nxy = g.pitch * g.ny;   // elements of one z plane (rows padded to the pitch)
+    constexpr int kRedWaves = (NC + 63) / 64;   // wavefronts holding collision threads
+    double nsum[RED ? 5 : 1];                   // the own node's totals (RED)
+    if constexpr (RED) {
+        if (tid < 5 * kRedWaves) red_lds[tid] = 0.0;
+    }
 
     // moment-stage slots of this thread: LDS index on the 2-halo region, on the 1-halo region
     // (m_f < 0 outside it) and wrapped x / y*nx of (node - c) for c = +1, 0, -1 (index 1 - c);
@@ -314,9 +326,9 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
             m_x[r][0] = wrap_index(gx - 1, g.nx);
             m_x[r][1] = gx;
             m_x[r][2] = wrap_index(gx + 1, g.nx);
-            m_y[r][0] = wrap_index(gy - 1, g.ny) * g.nx;
-            m_y[r][1] = gy * g.nx;
-            m_y[r][2] = wrap_index(gy + 1, g.ny) * g.nx;
+            m_y[r][0] = wrap_index(gy - 1, g.ny) * g.pitch;
+            m_y[r][1] = gy * g.pitch;
+            m_y[r][2] = wrap_index(gy + 1, g.ny) * g.pitch;
         }
     }
     int f_e[MF], f_f[MF];
@@ -492,7 +504,7 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
         constexpr bool WN = decltype(with_n)::value;
         const int sc = ring(zc), scm = ring(zc - 1), scp = ring(zc + 1);
         const int suc = uhring(zc), sucm = uzring(zc - 1), sucp = uzring(zc + 1);
-        const int own = wrap_index(zc, g.nz) * nxy + oy * g.nx + ox;
+        const int own = wrap_index(zc, g.nz) * nxy + oy * g.pitch + ox;
 
         const double rho_d = o_rho[ZH], E_d = o_E[ZH];
         const R rho = R(rho_d), E = R(E_d), T = sT[sc][of];
@@ -532,6 +544,10 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
         c.setup(rho, E, ux, uy, uz, Fo[0], Fo[1], Fo[2], inv_rho, dE, keepN, keepG, omega_E,
                 pseudo);
         c.mrt_prepare(pk_n, ph);
+        if constexpr (RED) {
+#pragma unroll
+            for (int q = 1; q < 4; ++q) nsum[q] = 0.0;
+        }
 #pragma unroll
         for (int k = 1; k < Q; ++k) {
             const int ko = opposite<Q>(k);
@@ -542,11 +558,24 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
             io.store(Q + k, own, out[1]);
             io.store(ko, own, out[2]);
             io.store(Q + ko, own, out[3]);
+            if constexpr (RED) {
+                // direction ko = -k: the pair's momentum is c_k (N_k - N_ko)
+                const double a = double(out[0]), b = double(out[2]);
+                if (L::cx[k] != 0) nsum[1] += L::cx[k] > 0 ? a - b : b - a;
+                if (L::cy[k] != 0) nsum[2] += L::cy[k] > 0 ? a - b : b - a;
+                if (L::cz[k] != 0) nsum[3] += L::cz[k] > 0 ? a - b : b - a;
+            }
         }
         S n0, g0;
         c.rest(rho_d, E_d, dE, n0, g0);
         io.store(0, own, n0);
         io.store(Q, own, g0);
+        if constexpr (RED) {
+            // the collision's own FP64 sums of the stored moving populations (which close the
+            // node's balances through the rest populations), plus the stored rest ones
+            nsum[0] = c.sumN + double(n0);
+            nsum[4] = c.sumG + double(g0);
+        }
     };
 
     // Chunks march upward and downward alternately, so the two chunks on either side of a
@@ -640,7 +669,19 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
         __syncthreads();
 
         // ---------------- C: energy source, collisions, store for plane zc = zm - dir ZH
-        if (collides) load_own(zc, WithN{});
+        if constexpr (D == 2) {
+            // one plane and no lag: the moment stage's pulls of slot 0 (the own node, the same
+            // loads) are still in registers
+            if (collides) {
+#pragma unroll
+                for (int k = 1; k < Q; ++k) {
+                    pk_e[k] = R(pe0[k]);
+                    pk_n[k] = NMODE != kTauOne ? R(pn0[k]) : R(0);
+                }
+            }
+        } else {
+            if (collides) load_own(zc, WithN{});
+        }
         if constexpr (kStash) {
             // plane zm takes the ring slot of plane zm - 2 dir, read just above by this same
             // thread (every thread touches only its own column of the stash)
@@ -650,22 +691,54 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
             }
         }
         if (collides) collide(zc, WithN{});
+        if constexpr (RED) {
+            // whole collision wavefronts (the condition is uniform over a wavefront)
+            if (it >= 2 * ZH && tid < 64 * kRedWaves) {
+                double v[5];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) v[q] = collides ? nsum[q] : 0.0;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) v[q] += __shfl_xor(v[q], off, 64);
+                }
+                if ((tid & 63) == 0) {
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) red_lds[(tid >> 6) * 5 + q] += v[q];
+                }
+            }
+        }
         if constexpr (!kFiveRing) __syncthreads();
     }
     // A caller that runs several tiles in one workgroup reuses the LDS rings: the next tile's
     // moment stage must not overwrite planes that a slower wave's last collision still reads.
     if constexpr (kFiveRing) __syncthreads();
+    if constexpr (RED) {
+        // the barrier above (D3Q19) or the one closing the last iteration (D2Q9) orders the
+        // wavefronts' last additions before these reads
+        if (tid < 5) {
+            double t = 0.0;
+            for (int w = 0; w < kRedWaves; ++w) t += red_lds[w * 5 + tid];
+            aux.partials[(long long)lb * 5 + tid] = t;
+        }
+    }
 }
 
 template <int Q, class S, class R, int TX, int TY, int NTH, bool PIPE, int ADDR, int NMODE,
-          bool STASH, int EXT>
+          bool STASH, int EXT, bool RED = false>
 __global__ void __launch_bounds__(NTH)
 k_step(const S* __restrict__ src, S* __restrict__ dst, const StepGeom g, const Phys ph,
        const StepAux aux)
 {
     __shared__ TileLds<Q, S, R, TX, TY, STASH> lds;
-    step_tile<Q, S, R, TX, TY, NTH, PIPE, ADDR, NMODE, STASH, EXT>(
-        lds, src, dst, g, ph, aux, xcd_logical_block(blockIdx.x, gridDim.x, g.resident));
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x, g.resident);
+    if constexpr (RED) {
+        __shared__ double red_lds[5 * ((TX * TY + 63) / 64)];
+        step_tile<Q, S, R, TX, TY, NTH, PIPE, ADDR, NMODE, STASH, EXT, true>(lds, src, dst, g, ph, aux,
+                                                                            lb, red_lds);
+    } else {
+        step_tile<Q, S, R, TX, TY, NTH, PIPE, ADDR, NMODE, STASH, EXT>(lds, src, dst, g, ph, aux, lb);
+    }
 }
 
 }  // namespace lbm

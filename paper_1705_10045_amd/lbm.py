@@ -75,6 +75,7 @@ _SIGNATURES = [
     ("lbm_moments_device", _ST, [_P, _P, _P, _P, _P]),
     ("lbm_moments_device_noalloc", _ST, [_P, _P, _P, _P, _P]),
     ("lbm_reduce", _ST, [_P, _D]),
+    ("lbm_step_reduce", _ST, [_P, ctypes.c_int, _D]),
     ("lbm_step_count", ctypes.c_longlong, [_P]),
     ("lbm_footprint_bytes", ctypes.c_size_t, [ctypes.POINTER(lbm_params)]),
     ("lbm_checkpoint", _ST, [_P, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
@@ -94,6 +95,7 @@ _SIGNATURES = [
                             ctypes.POINTER(ctypes.c_int)]),
     ("lbm_pool_collect", _ST, [_P, ctypes.c_longlong, _D, _D, _D, _D]),
     ("lbm_pool_stats", _ST, [_P, ctypes.POINTER(ctypes.c_longlong)]),
+    ("lbm_pool_totals", _ST, [_P, ctypes.c_longlong, _D, _D]),
     ("lbm_pool_destroy", _ST, [_P]),
 ]
 
@@ -220,6 +222,12 @@ def lbm_reduce(h):
     return out
 
 
+def lbm_step_reduce(h, nsteps):
+    out = np.zeros(5)
+    _check(lib().lbm_step_reduce(h, nsteps, _dp(out)))
+    return out
+
+
 def lbm_step_count(h):
     return lib().lbm_step_count(h)
 
@@ -303,6 +311,9 @@ class Sim:
 
     def reduce(self):
         return lbm_reduce(self._h)
+
+    def step_reduce(self, n=1):
+        return lbm_step_reduce(self._h, n)
 
     def checkpoint(self):
         return lbm_checkpoint(self._h)
@@ -394,6 +405,14 @@ def lbm_pool_collect(pool, ticket, shape):
     return {"rho": rho, "u_star": us, "E": E, "T": T}, st
 
 
+def lbm_pool_totals(pool, ticket):
+    """Totals (mass, momentum, energy) of a finished request at admission and at its end."""
+    initial = np.zeros(5)
+    final = np.zeros(5)
+    _check(lib().lbm_pool_totals(pool, int(ticket), _dp(initial), _dp(final)))
+    return initial, final
+
+
 def lbm_pool_stats(pool):
     out = (ctypes.c_longlong * 4)()
     _check(lib().lbm_pool_stats(pool, out))
@@ -432,6 +451,9 @@ class Pool:
     def collect(self, ticket):
         fields, st = lbm_pool_collect(self._h, ticket, self._shapes.pop(ticket))
         return fields, st
+
+    def totals(self, ticket):
+        return lbm_pool_totals(self._h, ticket)
 
     def stats(self):
         return lbm_pool_stats(self._h)

@@ -89,3 +89,28 @@ def test_pool_boiling_512_for_10000_steps():
     assert abs(drift) < 1e-6
     assert t1[4] > t0[4]
     assert m["T"][0].mean() > m["T"][-1].mean()
+
+
+def _host_available_bytes():
+    with open("/proc/meminfo") as f:
+        for line in f:
+            if line.startswith("MemAvailable:"):
+                return int(line.split()[1]) * 1024
+    return 0
+
+
+def test_pool_boiling_512_against_oracle():
+    """The 512^3 pool-boiling workload at full size in the launch the benchmark times, every
+    field against the oracle after one step (the oracle holds about 127 GB of host memory for
+    it: the test needs twice that available)."""
+    need = 2 * 0.95e3 * 512 ** 3
+    if _host_available_bytes() < need:
+        pytest.skip("the 512^3 oracle needs %.0f GB of available host memory" % (need / 1e9))
+    case = I.pool_boiling_3d(n=512)
+    print("pool boiling 512^3 vs oracle, 1 step", flush=True)
+    g = _moments_after(case, 1)
+    o, _ = run_oracle(case, 1)
+    errs = rel_errors(g, o)
+    del g, o
+    describe("pool boiling 512^3 4B, 1 step", errs)
+    assert max(errs.values()) < 1e-5

@@ -166,3 +166,35 @@ def test_admissions_and_collections_overlap_replay_in_flight():
             single = s.moments()
         for k in single:
             assert np.array_equal(results[r["id"]][k], single[k]), (r["id"], k)
+
+
+def test_per_request_totals():
+    """lbm_pool_totals: a finished request's totals at admission and at its end, as the single
+    simulation's lbm_reduce gives them (the pool's state equals the single simulation's bit for
+    bit, so they agree to the order of the FP64 sums), mass conserved over the run; a ticket
+    that is still running is refused."""
+    reqs = [_req(21, 32, 45, "droplet", 0.8), _req(22, 48, 30, "slab", 0.85)]
+    with lbm.Pool(2 * GIB, max_slots=4, steps_per_run=10) as pool:
+        tickets = []
+        for req in reqs:
+            f = I.request_fields(req)
+            tickets.append(pool.submit(f["params"], f["rho0"], f["u0"], f["T0"], req["steps"]))
+        pool.run()
+        with pytest.raises(lbm.LbmError) as e:
+            pool.totals(tickets[0])
+        assert e.value.status == lbm.LBM_EBUSY
+        for _ in range(4):
+            pool.run()
+        totals = [pool.totals(t) for t in tickets]
+        for t in tickets:
+            pool.collect(t)
+    for req, (t0, t1) in zip(reqs, totals):
+        f = I.request_fields(req)
+        with lbm.Sim(19, f["params"], f["rho0"], f["u0"], f["T0"], storage_bytes=4) as s:
+            r0 = s.reduce()
+            s.step(req["steps"])
+            r1 = s.reduce()
+        mass = r0[0]
+        assert np.abs(t0 - r0).max() <= 1e-12 * mass
+        assert np.abs(t1 - r1).max() <= 1e-12 * mass
+        assert abs(t1[0] - t0[0]) < 2e-8 * mass
