@@ -49,7 +49,7 @@ def bytes_per_update(Q, storage):
 KERNEL_SOURCES = ["paper_1705_10045_amd/csrc/step_kernel.hpp", "paper_1705_10045_amd/csrc/node_math.hpp",
                   "paper_1705_10045_amd/csrc/physics.hpp",
                   "paper_1705_10045_amd/csrc/lattice.hpp", "paper_1705_10045_amd/csrc/kernels.hip",
-                  "paper_1705_10045_amd/csrc/api.hip"]
+                  "paper_1705_10045_amd/csrc/step_launch.hpp", "paper_1705_10045_amd/csrc/api.hip"]
 
 
 def _code_only(text):

@@ -1,6 +1,7 @@
 """The full-size configurations on the GPU: states at the top of the buffer-resource range and
-beyond it, the 256^3 spinodal with FP64 populations against the oracle, and the 512^3 pool
-boiling over 10,000 steps.  Each test prints the case before its device work."""
+beyond it, the 256^3 spinodal with FP64 populations against the oracle, the 512^3 pool
+boiling over 10,000 steps and against the oracle, and cubes between the powers of two.  Each
+test prints the case before its device work."""
 import numpy as np
 import pytest
 
@@ -113,4 +114,24 @@ def test_pool_boiling_512_against_oracle():
     errs = rel_errors(g, o)
     del g, o
     describe("pool boiling 512^3 4B, 1 step", errs)
+    assert max(errs.values()) < 1e-5
+
+
+@pytest.mark.parametrize("n,chunks", [(288, 3), (300, 4)])
+def test_sizes_between_powers_of_two_against_oracle(n, chunks):
+    """Cubes between the powers of two in their automatic launch: 288^3 takes 3 z chunks of 96
+    (486 workgroups in two rounds), 300^3 has ragged tiles in x and y, rows padded from 300 to a
+    pitch of 320 and 4 chunks of 75, with global addressing (its padded state exceeds 4 GB).
+    Every field against the oracle after 2 steps."""
+    case = I.spinodal_3d(n=n, Tr=0.75, rho_mean=1.0, sigma=0.02)
+    print("spinodal %d^3 vs oracle, 2 steps" % n, flush=True)
+    with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"]) as s:
+        info = s.launch_info()
+        assert (info["chunk"], info["workgroups"]) == (-(-n // chunks), -(-n // 32) * -(-n // 16) * chunks)
+        s.step(2)
+        g = s.moments()
+    o, _ = run_oracle(case, 2)
+    errs = rel_errors(g, o)
+    del g, o, case
+    describe("spinodal %d^3 4B, 2 steps" % n, errs)
     assert max(errs.values()) < 1e-5

@@ -2,7 +2,8 @@
 of tests/scenarios.py run for a prefix the oracle can follow, element by element, and the two
 experiments whose whole content is a curve the oracle's closed forms give: the coexistence
 densities against the Maxwell construction (Fig. 4b) and the sound speeds against 1/C_V
-(Fig. 8, eq:sspeed)."""
+(Fig. 8, eq:sspeed); and the parasitic spreading of energy at phase boundaries without the
+pseudoforces (Fig. 1)."""
 import numpy as np
 import pytest
 from scipy.optimize import curve_fit
@@ -10,7 +11,7 @@ from scipy.optimize import curve_fit
 import oracle
 from paper_1705_10045_amd import inputs as I
 from paper_1705_10045_amd import lbm
-from parity import compare, describe
+from parity import compare, describe, rel_errors, run_gpu, run_oracle
 
 import scenarios as S
 
@@ -118,3 +119,43 @@ def test_sound_speed_against_heat_capacity():
     inv = 1.0 / np.array(cvs)
     fit = np.polyfit(inv, ms, 1)
     assert np.abs(np.polyval(fit, inv) - ms).max() < 2e-3 * max(ms)
+
+
+# Fig. 1 (section 4): a stationary one-dimensional drop in its saturated vapour, with pressure
+# work, conduction and latent heat off.  Without the pseudoforces the internal energy leaks from
+# the liquid into the vapour at the boundaries (temperature peaks in the vapour, drops in the
+# liquid); with them (tau_E = tau) the energy populations stay c_V T0 N_k and T stays T0.
+def _fig1_drop(flags, n=96, Tr=0.8):
+    shape = (1, 4, n)
+    rv, rl = I.coexistence(Tr)
+    rho = I.two_phase_smooth(I.slab_distance(shape, n / 6, 0), rl, rv)
+    p = I.physics(tau_E=1.0, flags=flags)
+    return dict(Q=9, params=p, rho0=rho, u0=I.uniform_velocity(shape, (0.0, 0.0, 0.0)),
+                T0=np.full(shape, Tr))
+
+
+@pytest.mark.parametrize("storage", [4, 8])
+def test_fig1_parasitic_spreading_and_pseudoforces(storage):
+    Tr = 0.8
+    case = _fig1_drop(I.PSEUDOFORCE)
+    print("Fig. 1: 1D drop, pseudoforces on, %dB, 2000 steps" % storage, flush=True)
+    g, _ = run_gpu(case, 2000, storage)
+    # FP64: the invariant to rounding; FP32: to the storage rounding of g and N, which need not
+    # round in proportion
+    assert np.abs(g["T"] - Tr).max() < (1e-12 if storage == 8 else 1e-4)
+
+    case = _fig1_drop(0)
+    print("Fig. 1: 1D drop, pseudoforces off, %dB, 10 steps" % storage, flush=True)
+    g, _ = run_gpu(case, 10, storage)
+    o, _ = run_oracle(case, 10)
+    errs = rel_errors(g, o)
+    describe("Fig. 1 leak, 10 steps, %dB" % storage, errs)
+    assert max(errs.values()) < (1e-5 if storage == 4 else 1e-11)
+    T = g["T"][0, 0]
+    rho = g["rho"][0, 0]
+    rv, rl = I.coexistence(Tr)
+    vapour = rho < rv + 0.1 * (rl - rv)
+    liquid = rho > rl - 0.1 * (rl - rv)
+    # peaks in the vapour and drops in the liquid next to the boundaries, of percents
+    assert T[vapour].max() > Tr * 1.01
+    assert T[liquid].min() < Tr * 0.99
