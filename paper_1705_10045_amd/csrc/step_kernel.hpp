@@ -455,18 +455,20 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
     const bool has_g = EXT != kExtNone && (ph.g[0] != 0.0 || ph.g[1] != 0.0 || ph.g[2] != 0.0);
 
     // the own node's pulls for the collision at plane zc (moving directions; the rest ones
-    // follow from the balances); with the stash the energy populations come from LDS
+    // follow from the balances): the density populations when the collision reads them
+    // (with_n), the energy populations (with_e), from the LDS stash when there is one
     R pk_n[Q], pk_e[Q];
-    auto load_own = [&](int zc, auto with_n) {
+    auto load_own = [&](int zc, auto with_n, auto with_e) {
         constexpr bool WN = decltype(with_n)::value;
-        if constexpr (kStash) {
+        constexpr bool WE = decltype(with_e)::value;
+        if constexpr (kStash && WE) {
 #pragma unroll
             for (int k = 1; k < Q; ++k) {
                 pk_e[k] = R(sG[zc & 1][k - 1][tid]);
-                pk_n[k] = R(0);
+                if constexpr (NMODE == kTauOne) pk_n[k] = R(0);
             }
-            if constexpr (!WN) return;
         }
+        if constexpr (!WN && (kStash || !WE)) return;
         const bool bb_lo = has_walls && zc == 0;
         const bool bb_hi = has_walls && zc == g.nz - 1;
         const int zoc = wrap_index(zc, g.nz) * nxy;
@@ -490,14 +492,18 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
                         off = row[1][1] + xs[1];
                     }
                 }
-                if constexpr (!kStash) pk_e[k] = R(io.load(Q + pk, off));
-                pk_n[k] = WN ? R(io.load(pk, off)) : R(0);
+                if constexpr (!kStash && WE) pk_e[k] = R(io.load(Q + pk, off));
+                if constexpr (WN) pk_n[k] = R(io.load(pk, off));
+                else pk_n[k] = R(0);
             }
         };
         if (bb_lo || bb_hi) pulls(std::true_type{});
         else pulls(std::false_type{});
     };
     using WithN = std::integral_constant<bool, NMODE != kTauOne>;
+    // with the stash and a collision that reads N_k, those pulls are issued before the force
+    // stage, whose LDS work then covers their latency (the stash read stays in the collision)
+    constexpr bool kEarlyN = kStash && NMODE != kTauOne;
 
     // energy source and both collisions of the own node at plane zc; stores the result
     auto collide = [&](int zc, auto with_n) {
@@ -631,6 +637,10 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
         }
         __syncthreads();
 
+        if constexpr (kEarlyN) {
+            if (collides) load_own(zc, std::true_type{}, std::false_type{});
+        }
+
         // ---------------- F: force and u* on the tile + 1-halo of plane zf = zm - dir ZH/2
         if (it >= ZH && beyond_wall(zm - dir * (ZH / 2))) {
             fprev[0] = fcur[0]; fprev[1] = fcur[1]; fprev[2] = fcur[2];
@@ -679,8 +689,10 @@ __device__ __forceinline__ void step_tile(TileLds<Q, S, R, TX, TY, STASH>& lds,
                     pk_n[k] = NMODE != kTauOne ? R(pn0[k]) : R(0);
                 }
             }
+        } else if constexpr (kEarlyN) {
+            if (collides) load_own(zc, std::false_type{}, std::true_type{});
         } else {
-            if (collides) load_own(zc, WithN{});
+            if (collides) load_own(zc, WithN{}, std::true_type{});
         }
         if constexpr (kStash) {
             // plane zm takes the ring slot of plane zm - 2 dir, read just above by this same
