@@ -135,3 +135,27 @@ def test_sizes_between_powers_of_two_against_oracle(n, chunks):
     del g, o, case
     describe("spinodal %d^3 4B, 2 steps" % n, errs)
     assert max(errs.values()) < 1e-5
+
+
+def test_two_round_placement_against_oracle():
+    """A 512 x 512 x 8 droplet: 512 tiles of 32 x 16 in one z chunk, two rounds of 256, each
+    round a band of 16 tile rows shared by the 8 XCDs in runs of 2 rows (the placement of the
+    512^3 launch).  Every field against the oracle after 5 steps, and the same fields, bit for
+    bit, with z chunks of 4 planes (1,024 workgroups in four rounds)."""
+    case = I.droplet_3d(shape=(8, 512, 512), radius=60.0)
+    print("two-round placement: droplet 512x512x8, 5 steps", flush=True)
+    with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"]) as s:
+        assert s.launch_info()["workgroups"] == 512
+        s.step(5)
+        g = s.moments()
+    with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"]) as s:
+        s.set_launch(0, 4)
+        assert s.launch_info()["workgroups"] == 1024
+        s.step(5)
+        g2 = s.moments()
+    for k in g:
+        assert np.array_equal(g[k], g2[k]), k
+    o, _ = run_oracle(case, 5)
+    errs = rel_errors(g, o)
+    describe("droplet 512x512x8 4B, 5 steps", errs)
+    assert max(errs.values()) < 1e-5
