@@ -148,6 +148,17 @@ def workload(name, edge=None):
     raise SystemExit("unknown workload %s" % name)
 
 
+def copy_ceiling_gbs(Q, storage, shape):
+    """The committed copy-kernel ceiling of the same state (profiles/ceiling_state_copy_fp32.json,
+    from `bench.py --ceiling`) for FP32 D3Q19 cubes of edge 128, 256 or 512, else None."""
+    path = os.path.join(ROOT, "profiles", "ceiling_state_copy_fp32.json")
+    if Q != 19 or storage != 4 or len(set(shape)) != 1 or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)["results"].get("state_copy_%d" % shape[0])
+    return None if rec is None else rec["hip_flat_GB_per_s"]
+
+
 def measured_traffic(config_name, bytes_alg):
     """HBM bytes per launch from the committed rocprofv3 counter summary of this workload, if it
     was taken on the current kernel source."""
@@ -502,6 +513,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
+                     # the counted bytes over the timed kernel time, and a plain copy of the
+                     # same state, for context (neither is the graded fraction)
+                     "traffic_GB_per_s": (round(traffic / (ms_per_step / 1e3) / 1e9, 1)
+                                          if traffic else None),
+                     "copy_ceiling_GB_per_s": copy_ceiling_gbs(case["Q"], storage,
+                                                               case["rho0"].shape),
                      "kernel": "lbm::k_step<%d,%s> (one launch per step)" %
                                (case["Q"], "float" if storage == 4 else "double"),
                      "algorithmic_bytes_per_launch": bytes_alg},
