@@ -198,3 +198,30 @@ def test_per_request_totals():
         assert np.abs(t0 - r0).max() <= 1e-12 * mass
         assert np.abs(t1 - r1).max() <= 1e-12 * mass
         assert abs(t1[0] - t0[0]) < 2e-8 * mass
+
+
+def test_pool_serves_walls_and_gravity_beside_periodic_requests():
+    """Pool-boiling requests (walls normal to z with held wall temperatures, gravity), at tau = 1
+    and tau != 1, run in the pool beside a periodic droplet: the periodic request goes through
+    the periodic launch and the others through the one with walls, and each result equals its
+    single simulation bit for bit."""
+    cases = [I.request_fields(_req(31, 32, 30, "droplet", 0.8)),
+             I.pool_boiling_3d(shape=(40, 32, 32), gravity=1e-4),
+             I.pool_boiling_3d(shape=(24, 20, 48), gravity=1e-4, params=I.physics(tau=0.8))]
+    steps = [30, 40, 25]
+    with lbm.Pool(2 * GIB, max_slots=4, steps_per_run=10) as pool:
+        tickets = [pool.submit(c["params"], c["rho0"], c["u0"], c["T0"], n)
+                   for c, n in zip(cases, steps)]
+        for _ in range(4):
+            pool.run()
+        results = []
+        for t in tickets:
+            fields, st = pool.collect(t)
+            assert st == lbm.LBM_OK
+            results.append(fields)
+    for c, n, res in zip(cases, steps, results):
+        with lbm.Sim(19, c["params"], c["rho0"], c["u0"], c["T0"], storage_bytes=4) as s:
+            s.step(n)
+            single = s.moments()
+        for k in res:
+            assert np.array_equal(res[k], single[k]), (c["rho0"].shape, k)
