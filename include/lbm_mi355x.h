@@ -262,8 +262,8 @@ lbm_status lbm_coexistence(double Tr, double* rho_v, double* rho_l);
 typedef struct lbm_pool lbm_pool;
 
 /* Create a pool on the current device.  params of submitted requests must use lattice 19,
- * storage 4, edges up to max_edge, the BGK collision and the van der Waals EOS; walls and
- * gravity are accepted (those requests run in a second launch of the batched step). */
+ * storage 4, edges up to max_edge and the van der Waals EOS; walls, gravity and the MRT
+ * collision are accepted (each kind of request runs in its own launch of the batched step). */
 lbm_status lbm_pool_create(size_t hbm_budget_bytes, int max_slots, int steps_per_run,
                            void* stream, lbm_pool** out);
 

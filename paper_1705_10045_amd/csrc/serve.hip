@@ -3,9 +3,9 @@
 //
 // Device side: a slot table (one SlotDesc per slot) and a flat work list of tiles: slot s owns
 // the global tile indices [tile_begin, tile_begin + ntiles).  One step of every active slot is
-// two launches of k_pool_step over a fixed grid that walks the work list (one for the periodic
-// requests, one for those with walls or gravity; a launch with no tile of its kind returns at
-// once), followed by k_pool_advance, which flips each slot's buffer parity, counts its steps
+// four launches of k_pool_step over a fixed grid that walks the work list (one per kind of
+// request: periodic or with walls or gravity, BGK or MRT; a launch with no tile of its kind
+// returns at once), followed by k_pool_advance, which flips each slot's buffer parity, counts its steps
 // down and retires it when done or when its error word is set.  steps_per_run such steps are
 // captured once into a HIP graph; admissions and collections only rewrite the slot table
 // between replays, so the graph is never re-captured.
@@ -49,7 +49,8 @@ struct SlotDesc {
     int ntiles;
     int parity;        // buf[parity] holds the current state
     int active;        // 1 while steps remain and no error was flagged
-    int ext;           // 1: walls or gravity (served by the kExtWalls instantiation)
+    int kind;          // launch that serves the slot: + 1 for walls or gravity (the kExtWalls
+                       // instantiation), + 2 for the MRT collision
     long long remaining;
     long long steps_done;
 };
@@ -57,18 +58,18 @@ struct SlotDesc {
 struct PoolHeader {
     int nslots;        // slots [0, nslots) are searched by the step kernel
     int total_tiles;
-    int kind_tiles[2]; // tiles of periodic requests [0] and of requests with walls or gravity [1]
+    int kind_tiles[4]; // tiles of the requests of each kind (SlotDesc::kind)
 };
 
-// EXTK: kExtNone serves the periodic requests, kExtWalls those with walls or gravity (two
-// launches per step, each skipping the other kind's tiles), so the periodic step keeps the
-// registers of its own instantiation.
-template <int EXTK>
+// One launch per kind of request (EXTK: kExtNone for periodic boxes, kExtWalls with walls or
+// gravity; MRT: the MRT collision instead of BGK), each skipping the other kinds' tiles, so the
+// common periodic BGK step keeps the registers of its own instantiation.
+template <int EXTK, bool MRT>
 __global__ void __launch_bounds__(kPoolThreads)
 k_pool_step(const SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ hdr,
             const double* __restrict__ table, double s0, double inv_ds, int* __restrict__ errs)
 {
-    constexpr int kKind = EXTK == kExtNone ? 0 : 1;
+    constexpr int kKind = (EXTK == kExtNone ? 0 : 1) + (MRT ? 2 : 0);
     if (hdr->kind_tiles[kKind] == 0) return;
     __shared__ TileLds<19, float, float, kPoolTX, kPoolTY, true> lds;
     const int total = hdr->total_tiles;
@@ -83,7 +84,7 @@ k_pool_step(const SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ h
             if (slots[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
         }
         const SlotDesc& d = slots[lo];
-        if (!d.active || t - d.tile_begin >= d.ntiles || d.ext != kKind) continue;
+        if (!d.active || t - d.tile_begin >= d.ntiles || d.kind != kKind) continue;
         // workgroup-uniform copies, so the stores of the step cannot alias them
         const StepGeom g = d.geom;
         const Phys ph = d.phys;
@@ -99,9 +100,12 @@ k_pool_step(const SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ h
         aux.eos_p = nullptr;
         aux.eos_coex = nullptr;
         aux.partials = nullptr;
-        // each request's own collision: tau = 1 (with the density prefetch) or general; both
-        // share the workgroup's LDS
-        if (ph.omega == 1.0)
+        // each request's own collision: MRT, or BGK with tau = 1 (with the density prefetch)
+        // or general; all share the workgroup's LDS
+        if constexpr (MRT)
+            step_tile<19, float, float, kPoolTX, kPoolTY, kPoolThreads, false, kAddrBuf, kMrt, true, EXTK>(
+                lds, src, dst, g, ph, aux, local);
+        else if (ph.omega == 1.0)
             step_tile<19, float, float, kPoolTX, kPoolTY, kPoolThreads, true, kAddrBuf, kTauOne, true, EXTK>(
                 lds, src, dst, g, ph, aux, local);
         else
@@ -237,14 +241,14 @@ StepGeom pool_geometry(const lbm_params& p)
 // Rebuild the work list (tile prefix over slots in index order) and upload the table.
 lbm_status upload_table(lbm_pool* p)
 {
-    int total = 0, nslots = 0, kind_tiles[2] = {0, 0};
+    int total = 0, nslots = 0, kind_tiles[4] = {0, 0, 0, 0};
     for (int s = 0; s < p->max_slots; ++s) {
         SlotDesc& d = p->table[s];
         d.tile_begin = total;
         if (p->slots[s].used && d.active) {
             d.ntiles = d.geom.ntx * d.geom.nty * d.geom.nchunks;
             total += d.ntiles;
-            kind_tiles[d.ext] += d.ntiles;
+            kind_tiles[d.kind] += d.ntiles;
             nslots = s + 1;
         } else {
             d.ntiles = 0;
@@ -255,8 +259,7 @@ lbm_status upload_table(lbm_pool* p)
     // replay, which the stream orders after these copies, has completed
     p->h_hdr->nslots = nslots;
     p->h_hdr->total_tiles = total;
-    p->h_hdr->kind_tiles[0] = kind_tiles[0];
-    p->h_hdr->kind_tiles[1] = kind_tiles[1];
+    for (int k = 0; k < 4; ++k) p->h_hdr->kind_tiles[k] = kind_tiles[k];
     memcpy(p->h_up, p->table.data(), sizeof(SlotDesc) * p->max_slots);
     hipError_t e = hipMemcpyAsync(p->d_slots, p->h_up, sizeof(SlotDesc) * p->max_slots,
                                   hipMemcpyHostToDevice, p->stream);
@@ -272,9 +275,13 @@ lbm_status capture_graph(lbm_pool* p)
     if (e != hipSuccess) return hip_fail(e, "graph capture begin");
     const int adv_blocks = (p->max_slots + 255) / 256;
     for (int i = 0; i < p->steps_per_run; ++i) {
-        hipLaunchKernelGGL(k_pool_step<kExtNone>, dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
+        hipLaunchKernelGGL((k_pool_step<kExtNone, false>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
                            p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
-        hipLaunchKernelGGL(k_pool_step<kExtWalls>, dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
+        hipLaunchKernelGGL((k_pool_step<kExtWalls, false>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
+                           p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
+        hipLaunchKernelGGL((k_pool_step<kExtNone, true>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
+                           p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
+        hipLaunchKernelGGL((k_pool_step<kExtWalls, true>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
                            p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
         hipLaunchKernelGGL(k_pool_advance, dim3(adv_blocks), dim3(256), 0, p->stream, p->d_slots,
                            p->d_hdr, p->d_errs);
@@ -426,8 +433,8 @@ lbm_status lbm_pool_submit(lbm_pool* p, const lbm_params* params, const double* 
         set_error("pool requests must be D3Q19, FP32 storage, edges <= %d", kPoolMaxEdge);
         return LBM_EINVAL;
     }
-    if (params->collision != LBM_COLLISION_BGK || params->eos != LBM_EOS_VDW) {
-        set_error("pool requests use the BGK collision and the van der Waals EOS");
+    if (params->eos != LBM_EOS_VDW) {
+        set_error("pool requests use the van der Waals EOS");
         return LBM_EINVAL;
     }
     st = validate_fields(*params, rho0, u0, T0);
@@ -459,8 +466,9 @@ lbm_status lbm_pool_submit(lbm_pool* p, const lbm_params* params, const double* 
     d.phys = make_phys(*params);
     d.parity = 0;
     d.active = 1;
-    d.ext = (params->walls || params->gravity[0] != 0.0 || params->gravity[1] != 0.0 ||
-             params->gravity[2] != 0.0) ? 1 : 0;
+    d.kind = ((params->walls || params->gravity[0] != 0.0 || params->gravity[1] != 0.0 ||
+               params->gravity[2] != 0.0) ? 1 : 0) +
+             (params->collision == LBM_COLLISION_MRT ? 2 : 0);
     d.remaining = nsteps;
     const long long n = (long long)params->nx * params->ny * params->nz;
     // on the side stream: a replay in flight does not touch this free arena block or this

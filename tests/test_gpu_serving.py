@@ -225,3 +225,32 @@ def test_pool_serves_walls_and_gravity_beside_periodic_requests():
             single = s.moments()
         for k in res:
             assert np.array_equal(res[k], single[k]), (c["rho0"].shape, k)
+
+
+def test_pool_serves_mrt_requests():
+    """MRT requests (periodic, and with walls and gravity) beside a BGK one: each kind runs in
+    its own launch of the batched step, and each result equals its single simulation bit for
+    bit."""
+    rates = dict(collision=lbm.LBM_COLLISION_MRT, s_e=1.19, s_eps=1.4, s_q=1.2, s_m=1.98)
+    mrt = I.request_fields(_req(41, 32, 30, "droplet", 0.8), I.physics(tau=0.8))
+    mrt["params"] = dict(mrt["params"], **rates)
+    mrt_walls = I.pool_boiling_3d(shape=(24, 20, 40), gravity=1e-4, params=I.physics(tau=0.7))
+    mrt_walls["params"] = dict(mrt_walls["params"], **rates)
+    cases = [I.request_fields(_req(42, 48, 20, "slab", 0.85)), mrt, mrt_walls]
+    steps = [20, 30, 25]
+    with lbm.Pool(2 * GIB, max_slots=4, steps_per_run=10) as pool:
+        tickets = [pool.submit(c["params"], c["rho0"], c["u0"], c["T0"], n)
+                   for c, n in zip(cases, steps)]
+        for _ in range(3):
+            pool.run()
+        results = []
+        for t in tickets:
+            fields, st = pool.collect(t)
+            assert st == lbm.LBM_OK
+            results.append(fields)
+    for c, n, res in zip(cases, steps, results):
+        with lbm.Sim(19, c["params"], c["rho0"], c["u0"], c["T0"], storage_bytes=4) as s:
+            s.step(n)
+            single = s.moments()
+        for k in res:
+            assert np.array_equal(res[k], single[k]), (c["rho0"].shape, k)
