@@ -3,12 +3,12 @@
 //
 // Device side: a slot table (one SlotDesc per slot) and a flat work list of tiles: slot s owns
 // the global tile indices [tile_begin, tile_begin + ntiles).  One step of every active slot is
-// four launches of k_pool_step over a fixed grid that walks the work list (one per kind of
-// request: periodic or with walls or gravity, BGK or MRT; a launch with no tile of its kind
-// returns at once), followed by k_pool_advance, which flips each slot's buffer parity, counts its steps
-// down and retires it when done or when its error word is set.  steps_per_run such steps are
-// captured once into a HIP graph; admissions and collections only rewrite the slot table
-// between replays, so the graph is never re-captured.
+// one launch of k_pool_step per kind of request present (periodic or with walls or gravity,
+// BGK or MRT) over a fixed grid that walks the work list, followed by k_pool_advance, which
+// flips each slot's buffer parity, counts its steps down and retires it when done or when its
+// error word is set.  steps_per_run such steps are captured into a HIP graph, one graph per set
+// of kinds, each captured once on first use; admissions and collections only rewrite the slot
+// table between replays.
 //
 // Host side: first-fit allocation of slot buffers inside one arena allocated at creation
 // (admission by footprint never calls the allocator of the runtime), tickets, and the
@@ -166,8 +166,11 @@ struct lbm_pool {
     double* d_scratch = nullptr;             // moment scratch (10 n doubles)
     double* d_red = nullptr;                 // reduction partials (kPoolRedBlocks x 5)
     double* d_totals = nullptr;              // per slot: totals at admission, then at the end
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // one graph per set of request kinds present (bit k: a slot of SlotDesc::kind k is
+    // active), captured on first use, so a replay launches only the kinds it serves
+    hipGraph_t graph[16] = {};
+    hipGraphExec_t exec[16] = {};
+    int kinds = 0;                           // kind set of the uploaded table
     bool dirty = true;
     long long next_ticket = 1;
     std::map<long long, int> ticket_slot;
@@ -241,7 +244,7 @@ StepGeom pool_geometry(const lbm_params& p)
 // Rebuild the work list (tile prefix over slots in index order) and upload the table.
 lbm_status upload_table(lbm_pool* p)
 {
-    int total = 0, nslots = 0, kind_tiles[4] = {0, 0, 0, 0};
+    int total = 0, nslots = 0, kind_tiles[4] = {0, 0, 0, 0}, kinds = 0;
     for (int s = 0; s < p->max_slots; ++s) {
         SlotDesc& d = p->table[s];
         d.tile_begin = total;
@@ -249,6 +252,7 @@ lbm_status upload_table(lbm_pool* p)
             d.ntiles = d.geom.ntx * d.geom.nty * d.geom.nchunks;
             total += d.ntiles;
             kind_tiles[d.kind] += d.ntiles;
+            kinds |= 1 << d.kind;
             nslots = s + 1;
         } else {
             d.ntiles = 0;
@@ -265,30 +269,37 @@ lbm_status upload_table(lbm_pool* p)
                                   hipMemcpyHostToDevice, p->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(p->d_hdr, p->h_hdr, sizeof(PoolHeader), hipMemcpyHostToDevice, p->stream);
     if (e != hipSuccess) return hip_fail(e, "pool table upload");
+    p->kinds = kinds;
     p->dirty = false;
     return LBM_OK;
 }
 
-lbm_status capture_graph(lbm_pool* p)
+// Captures steps_per_run steps of the kinds in `kinds` (one launch per kind, then the advance)
+// into the graph of that kind set.  Called with no replay in flight on the pool's stream.
+lbm_status capture_graph(lbm_pool* p, int kinds)
 {
     hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "graph capture begin");
     const int adv_blocks = (p->max_slots + 255) / 256;
     for (int i = 0; i < p->steps_per_run; ++i) {
-        hipLaunchKernelGGL((k_pool_step<kExtNone, false>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
-                           p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
-        hipLaunchKernelGGL((k_pool_step<kExtWalls, false>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
-                           p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
-        hipLaunchKernelGGL((k_pool_step<kExtNone, true>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
-                           p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
-        hipLaunchKernelGGL((k_pool_step<kExtWalls, true>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
-                           p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
+        if (kinds & 1)
+            hipLaunchKernelGGL((k_pool_step<kExtNone, false>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
+                               p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
+        if (kinds & 2)
+            hipLaunchKernelGGL((k_pool_step<kExtWalls, false>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
+                               p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
+        if (kinds & 4)
+            hipLaunchKernelGGL((k_pool_step<kExtNone, true>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
+                               p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
+        if (kinds & 8)
+            hipLaunchKernelGGL((k_pool_step<kExtWalls, true>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
+                               p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
         hipLaunchKernelGGL(k_pool_advance, dim3(adv_blocks), dim3(256), 0, p->stream, p->d_slots,
                            p->d_hdr, p->d_errs);
     }
-    e = hipStreamEndCapture(p->stream, &p->graph);
+    e = hipStreamEndCapture(p->stream, &p->graph[kinds]);
     if (e != hipSuccess) return hip_fail(e, "graph capture end");
-    e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&p->exec[kinds], p->graph[kinds], nullptr, nullptr, 0);
     if (e != hipSuccess) return hip_fail(e, "graph instantiate");
     return LBM_OK;
 }
@@ -334,8 +345,12 @@ lbm_status launch_replay(lbm_pool* p)
     bool any = false;
     for (int s = 0; s < p->max_slots; ++s) any = any || (p->slots[s].used && p->table[s].active);
     if (!any) return LBM_OK;
+    if (!p->exec[p->kinds]) {
+        st = capture_graph(p, p->kinds);
+        if (st != LBM_OK) return st;
+    }
     for (int s = 0; s < p->max_slots; ++s) p->launched[s] = p->slots[s].used ? p->slots[s].ticket : -1;
-    hipError_t e = hipGraphLaunch(p->exec, p->stream);
+    hipError_t e = hipGraphLaunch(p->exec[p->kinds], p->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->h_rb, p->d_slots, sizeof(SlotDesc) * p->max_slots, hipMemcpyDeviceToHost, p->stream);
     if (e == hipSuccess)
@@ -414,8 +429,9 @@ lbm_status lbm_pool_create(size_t hbm_budget_bytes, int max_slots, int steps_per
     if (e == hipSuccess) e = hipMemsetAsync(p->d_errs, 0, sizeof(int) * max_slots, p->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) { lbm_status r = hip_fail(e, "pool setup"); lbm_pool_destroy(p); return r; }
+    // the graph of the common kind set (periodic BGK requests only) up front
     lbm_status st = upload_table(p);
-    if (st == LBM_OK) st = capture_graph(p);
+    if (st == LBM_OK) st = capture_graph(p, 1);
     if (st != LBM_OK) { lbm_pool_destroy(p); return st; }
     *out = p;
     return LBM_OK;
@@ -612,8 +628,10 @@ lbm_status lbm_pool_destroy(lbm_pool* p)
     (void)hipSetDevice(p->device);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     if (p->side) (void)hipStreamSynchronize(p->side);
-    if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
+    for (int k = 0; k < 16; ++k) {
+        if (p->exec[k]) (void)hipGraphExecDestroy(p->exec[k]);
+        if (p->graph[k]) (void)hipGraphDestroy(p->graph[k]);
+    }
     if (p->arena) (void)hipFree(p->arena);
     if (p->d_slots) (void)hipFree(p->d_slots);
     if (p->d_hdr) (void)hipFree(p->d_hdr);
