@@ -229,12 +229,18 @@ const char* lbm_last_error(void);
  * number of workgroups per step (for profiling reports). */
 lbm_status lbm_launch_info(const lbm_sim* sim, int info[4]);
 
+/* The launch lbm_init chooses for these parameters (default variant, automatic z chunk) on a
+ * device with `cus` compute units (256 on MI355X), in the layout of lbm_launch_info.  Host
+ * arithmetic only: touches no device and validates only the lattice, storage and shape
+ * (LBM_EINVAL otherwise).  The z chunk minimises the number of rounds of resident workgroups
+ * times (chunk + 4) planes, the moment stage's halo planes included. */
+lbm_status lbm_launch_plan(const lbm_params* params, int cus, int info[4]);
+
 /* Select the launch variant of the fused step kernel (0 .. n-1: tile shape, threads per
  * workgroup, prefetch or LDS stash; D3Q19 has seven with FP32 populations and four with FP64,
  * D2Q9 three: 32x8, 32x16 and 64x8 tiles) and the z-chunk length (0 = automatic).  The default
- * is variant 0, except 2 for D2Q9 FP32 boxes of 2^19 nodes and more.  Results do not depend on the choice (the
- * per-node arithmetic is the same); only speed does.  LBM_EINVAL for an unknown variant or a
- * negative chunk. */
+ * is variant 0.  Results do not depend on the choice (the per-node arithmetic is the same);
+ * only speed does.  LBM_EINVAL for an unknown variant or a negative chunk. */
 lbm_status lbm_set_launch(lbm_sim* sim, int variant, int chunk);
 
 /* Velocity set used by the library (section 2) and the force coefficients of section 3:

@@ -351,21 +351,22 @@ lbm_status validate_fields(const lbm_params& p, const double* rho0, const double
 
 // Launch geometry: tiles of the selected variant and z chunks sized so that one round of
 // workgroups fills the GPU, unless a chunk length is given.
-void choose_geometry(lbm_sim* s, int chunk_request)
+// The launch of the fused step for these parameters, launch variant and z-chunk request
+// (0 = automatic) on a device with `cus` compute units; host arithmetic only.
+StepGeom plan_geometry(const lbm_params& p, int variant, int chunk_request, int cus, int& tx, int& ty)
 {
-    const lbm_params& p = s->p;
-    int tx, ty, per_cu;
-    step_tile(p.lattice, p.storage_bytes, s->variant, tx, ty, per_cu);
-    StepGeom& g = s->geom;
+    int per_cu;
+    step_tile(p.lattice, p.storage_bytes, variant, tx, ty, per_cu);
+    StepGeom g{};
     g.nx = p.nx; g.ny = p.ny; g.nz = p.nz;
     g.pitch = row_pitch(p.nx, p.storage_bytes);
-    g.plane = s->plane;
+    g.plane = padded_plane(plane_elements(p));
     g.ntx = (p.nx + tx - 1) / tx;
     g.nty = (p.ny + ty - 1) / ty;
     int chunk = p.nz;
     // workgroups the device holds at once: the launch runs in rounds of this many, and the
     // kernel gives each round a contiguous band of tiles
-    g.resident = s->cus * per_cu;
+    g.resident = cus * per_cu;
     if (p.lattice == 19) {
         // z chunks.  Each chunk runs the moment stage on 4 planes outside it (2 on each side),
         // and the launch runs in rounds of `target` workgroups (later ones start as earlier
@@ -376,7 +377,7 @@ void choose_geometry(lbm_sim* s, int chunk_request)
         // workgroups in two nearly full rounds, instead of 324 in one full and one quarter
         // round), and powers of two keep one round of long chunks.
         const long long cols = (long long)g.ntx * g.nty;
-        const long long target = (long long)s->cus * per_cu;
+        const long long target = (long long)cus * per_cu;
         const long long maxc = p.nz / 4 > 0 ? p.nz / 4 : 1;
         long long best_cost = -1;
         for (long long nc = 1; nc <= maxc; ++nc) {
@@ -393,6 +394,14 @@ void choose_geometry(lbm_sim* s, int chunk_request)
     }
     g.chunk = chunk;
     g.nchunks = (p.nz + chunk - 1) / chunk;
+    return g;
+}
+
+void choose_geometry(lbm_sim* s, int chunk_request)
+{
+    int tx, ty;
+    s->geom = plan_geometry(s->p, s->variant, chunk_request, s->cus, tx, ty);
+    s->geom.plane = s->plane;
     s->tile_x = tx;
     s->tile_y = ty;
 }
@@ -607,6 +616,24 @@ lbm_status lbm_set_launch(lbm_sim* s, int variant, int chunk)
     }
     s->variant = variant;
     choose_geometry(s, chunk);
+    return LBM_OK;
+}
+
+lbm_status lbm_launch_plan(const lbm_params* p, int cus, int info[4])
+{
+    clear_error();
+    if (!p || !info || cus < 1) { set_error("NULL argument or compute-unit count below 1"); return LBM_EINVAL; }
+    if (!((p->lattice == 9 && p->nz == 1) || p->lattice == 19) ||
+        (p->storage_bytes != 4 && p->storage_bytes != 8) || p->nx < 1 || p->ny < 1 || p->nz < 1) {
+        set_error("lattice, storage or shape not supported");
+        return LBM_EINVAL;
+    }
+    int tx, ty;
+    const StepGeom g = plan_geometry(*p, 0, 0, cus, tx, ty);
+    info[0] = tx;
+    info[1] = ty;
+    info[2] = g.chunk;
+    info[3] = g.ntx * g.nty * g.nchunks;
     return LBM_OK;
 }
 

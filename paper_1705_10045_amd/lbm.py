@@ -83,6 +83,7 @@ _SIGNATURES = [
     ("lbm_free", _ST, [_P]),
     ("lbm_last_error", ctypes.c_char_p, []),
     ("lbm_launch_info", _ST, [_P, ctypes.POINTER(ctypes.c_int)]),
+    ("lbm_launch_plan", _ST, [ctypes.POINTER(lbm_params), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     ("lbm_set_launch", _ST, [_P, ctypes.c_int, ctypes.c_int]),
     ("lbm_lattice_info", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D, _D, _D]),
     ("lbm_coexistence", _ST, [ctypes.c_double, _D, _D]),
@@ -260,6 +261,14 @@ def lbm_last_error():
 def lbm_launch_info(h):
     info = (ctypes.c_int * 4)()
     _check(lib().lbm_launch_info(h, info))
+    return {"tile_x": info[0], "tile_y": info[1], "chunk": info[2], "workgroups": info[3]}
+
+
+def lbm_launch_plan(Q, shape, physics, storage_bytes=4, cus=256):
+    """The launch lbm_init would choose for this box (host only, no device)."""
+    params = make_params(Q, shape, physics, storage_bytes)
+    info = (ctypes.c_int * 4)()
+    _check(lib().lbm_launch_plan(ctypes.byref(params), int(cus), info))
     return {"tile_x": info[0], "tile_y": info[1], "chunk": info[2], "workgroups": info[3]}
 
 

@@ -155,3 +155,43 @@ def test_init_rejects_walls_on_d2q9():
     st = lbm.lib().lbm_init(ctypes.byref(p), None, None, None, None, ctypes.byref(h))
     assert st == lbm.LBM_EINVAL
     assert "walls need D3Q19" in lbm.lbm_last_error()
+
+
+def _rounds_cost(nz, cols, target=256):
+    """Rounds of `target` resident workgroups times (chunk + 4) planes for every chunk count:
+    the launch plan must take a chunk of least cost (fewest chunks among equals)."""
+    best = None
+    for nc in range(1, max(nz // 4, 1) + 1):
+        c = -(-nz // nc)
+        chunks = -(-nz // c)
+        cost = -(-cols * chunks // target) * (c + 4)
+        if best is None or cost < best[0]:
+            best = (cost, c)
+    return best[1]
+
+
+@pytest.mark.parametrize("shape,expect", [
+    ((512, 512, 512), (32, 16, 512, 512)),
+    ((128, 128, 128), (32, 16, 16, 256)),
+    ((256, 256, 256), (32, 16, 128, 256)),
+    ((288, 288, 288), (32, 16, 96, 486)),
+    ((320, 320, 320), (32, 16, 64, 1000)),
+    ((300, 300, 300), (32, 16, 75, 760)),
+])
+def test_launch_plan_of_d3q19_boxes(shape, expect):
+    """The host-only launch plan (no device): 32 x 16 tiles, and the z chunk that minimises the
+    rounds of 256 resident workgroups times the chunk plus its 4 halo planes."""
+    plan = lbm.lbm_launch_plan(19, shape, I.physics(), 4)
+    assert (plan["tile_x"], plan["tile_y"], plan["chunk"], plan["workgroups"]) == expect
+    cols = -(-shape[2] // 32) * -(-shape[1] // 16)
+    assert plan["chunk"] == _rounds_cost(shape[0], cols)
+
+
+def test_launch_plan_of_d2q9_and_fp64():
+    d2 = lbm.lbm_launch_plan(9, (1, 1000, 1000), I.physics(), 4)
+    assert (d2["tile_x"], d2["tile_y"], d2["chunk"], d2["workgroups"]) == (32, 8, 1, 32 * 125)
+    d64 = lbm.lbm_launch_plan(19, (256, 256, 256), I.physics(), 8)
+    assert (d64["tile_x"], d64["tile_y"]) == (32, 8)
+    assert d64["workgroups"] == 8 * 32 * (-(-256 // d64["chunk"]))
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_launch_plan(9, (2, 8, 8), I.physics(), 4)     # D2Q9 needs nz = 1
