@@ -119,7 +119,8 @@ typedef struct {
      * j, the band of the latent heat (section 5), linear in T~ between rows; the latent source
      * acts over the table's whole temperature range (rho_1 = rho_2 leaves a row without band).
      * Both host arrays are read by lbm_init, which keeps its own device copy; eos_nrho >= 4,
-     * eos_nT >= 2, at most 2^26 points.  Not accepted by the serving pool. */
+     * eos_nT >= 2, at most 2^26 points.  lbm_pool_submit likewise keeps a device copy with
+     * the request. */
     int eos;
     const double* eos_p;
     const double* eos_coex;
@@ -268,13 +269,15 @@ lbm_status lbm_coexistence(double Tr, double* rho_v, double* rho_l);
 typedef struct lbm_pool lbm_pool;
 
 /* Create a pool on the current device.  params of submitted requests must use lattice 19,
- * storage 4, edges up to max_edge and the van der Waals EOS; walls, gravity and the MRT
- * collision are accepted (each kind of request runs in its own launch of the batched step). */
+ * storage 4 and edges up to max_edge; walls, gravity, a tabulated EOS and the MRT collision are
+ * accepted (each kind of request runs in its own launch of the batched step). */
 lbm_status lbm_pool_create(size_t hbm_budget_bytes, int max_slots, int steps_per_run,
                            void* stream, lbm_pool** out);
 
-/* Admit a request (fields as for lbm_init).  *ticket identifies it.  LBM_EBUSY if no slot is
- * free or its footprint exceeds the remaining budget (nothing is allocated then). */
+/* Admit a request (fields as for lbm_init).  *ticket identifies it.  Its footprint is its two
+ * population buffers plus, with a tabulated EOS, its own copy of the table (the caller's arrays
+ * are read during the call only).  LBM_EBUSY if no slot is free or its footprint exceeds the
+ * remaining budget (nothing is allocated then). */
 lbm_status lbm_pool_submit(lbm_pool* pool, const lbm_params* params, const double* rho0,
                            const double* u0, const double* T0, long long nsteps,
                            long long* ticket);

@@ -49,8 +49,11 @@ struct SlotDesc {
     int ntiles;
     int parity;        // buf[parity] holds the current state
     int active;        // 1 while steps remain and no error was flagged
-    int kind;          // launch that serves the slot: + 1 for walls or gravity (the kExtWalls
-                       // instantiation), + 2 for the MRT collision
+    int kind;          // launch that serves the slot: kind_of(ext, mrt), ext 0 periodic, 1 walls
+                       // or gravity (kExtWalls), 2 a tabulated EOS (kExtTable), mrt the MRT
+                       // collision
+    const double* eos_p;     // tabulated EOS: the request's copy of the table in the arena
+    const double* eos_coex;
     long long remaining;
     long long steps_done;
 };
@@ -58,18 +61,22 @@ struct SlotDesc {
 struct PoolHeader {
     int nslots;        // slots [0, nslots) are searched by the step kernel
     int total_tiles;
-    int kind_tiles[4]; // tiles of the requests of each kind (SlotDesc::kind)
+    int kind_tiles[6]; // tiles of the requests of each kind (SlotDesc::kind)
 };
 
+constexpr int kPoolKinds = 6;
+__host__ __device__ constexpr int kind_of(int ext, bool mrt) { return ext + (mrt ? 3 : 0); }
+
 // One launch per kind of request (EXTK: kExtNone for periodic boxes, kExtWalls with walls or
-// gravity; MRT: the MRT collision instead of BGK), each skipping the other kinds' tiles, so the
-// common periodic BGK step keeps the registers of its own instantiation.
+// gravity, kExtTable with a tabulated EOS; MRT: the MRT collision instead of BGK), each skipping
+// the other kinds' tiles, so the common periodic BGK step keeps the registers of its own
+// instantiation.
 template <int EXTK, bool MRT>
 __global__ void __launch_bounds__(kPoolThreads)
 k_pool_step(const SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ hdr,
             const double* __restrict__ table, double s0, double inv_ds, int* __restrict__ errs)
 {
-    constexpr int kKind = (EXTK == kExtNone ? 0 : 1) + (MRT ? 2 : 0);
+    constexpr int kKind = kind_of(EXTK == kExtNone ? 0 : (EXTK == kExtWalls ? 1 : 2), MRT);
     if (hdr->kind_tiles[kKind] == 0) return;
     __shared__ TileLds<19, float, float, kPoolTX, kPoolTY, true> lds;
     const int total = hdr->total_tiles;
@@ -97,8 +104,8 @@ k_pool_step(const SlotDesc* __restrict__ slots, const PoolHeader* __restrict__ h
         aux.tab_s0 = s0;
         aux.tab_inv_ds = inv_ds;
         aux.err = errs + lo;
-        aux.eos_p = nullptr;
-        aux.eos_coex = nullptr;
+        aux.eos_p = d.eos_p;
+        aux.eos_coex = d.eos_coex;
         aux.partials = nullptr;
         // each request's own collision: MRT, or BGK with tau = 1 (with the density prefetch)
         // or general; all share the workgroup's LDS
@@ -168,8 +175,8 @@ struct lbm_pool {
     double* d_totals = nullptr;              // per slot: totals at admission, then at the end
     // one graph per set of request kinds present (bit k: a slot of SlotDesc::kind k is
     // active), captured on first use, so a replay launches only the kinds it serves
-    hipGraph_t graph[16] = {};
-    hipGraphExec_t exec[16] = {};
+    hipGraph_t graph[1 << kPoolKinds] = {};
+    hipGraphExec_t exec[1 << kPoolKinds] = {};
     int kinds = 0;                           // kind set of the uploaded table
     bool dirty = true;
     long long next_ticket = 1;
@@ -244,7 +251,7 @@ StepGeom pool_geometry(const lbm_params& p)
 // Rebuild the work list (tile prefix over slots in index order) and upload the table.
 lbm_status upload_table(lbm_pool* p)
 {
-    int total = 0, nslots = 0, kind_tiles[4] = {0, 0, 0, 0}, kinds = 0;
+    int total = 0, nslots = 0, kind_tiles[kPoolKinds] = {}, kinds = 0;
     for (int s = 0; s < p->max_slots; ++s) {
         SlotDesc& d = p->table[s];
         d.tile_begin = total;
@@ -263,7 +270,7 @@ lbm_status upload_table(lbm_pool* p)
     // replay, which the stream orders after these copies, has completed
     p->h_hdr->nslots = nslots;
     p->h_hdr->total_tiles = total;
-    for (int k = 0; k < 4; ++k) p->h_hdr->kind_tiles[k] = kind_tiles[k];
+    for (int k = 0; k < kPoolKinds; ++k) p->h_hdr->kind_tiles[k] = kind_tiles[k];
     memcpy(p->h_up, p->table.data(), sizeof(SlotDesc) * p->max_slots);
     hipError_t e = hipMemcpyAsync(p->d_slots, p->h_up, sizeof(SlotDesc) * p->max_slots,
                                   hipMemcpyHostToDevice, p->stream);
@@ -282,18 +289,17 @@ lbm_status capture_graph(lbm_pool* p, int kinds)
     if (e != hipSuccess) return hip_fail(e, "graph capture begin");
     const int adv_blocks = (p->max_slots + 255) / 256;
     for (int i = 0; i < p->steps_per_run; ++i) {
-        if (kinds & 1)
-            hipLaunchKernelGGL((k_pool_step<kExtNone, false>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
-                               p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
-        if (kinds & 2)
-            hipLaunchKernelGGL((k_pool_step<kExtWalls, false>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
-                               p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
-        if (kinds & 4)
-            hipLaunchKernelGGL((k_pool_step<kExtNone, true>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
-                               p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
-        if (kinds & 8)
-            hipLaunchKernelGGL((k_pool_step<kExtWalls, true>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,
-                               p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
+#define LBM_POOL_LAUNCH(EXTK, MRT)                                                                       \
+    if (kinds & (1 << kind_of(EXTK == kExtNone ? 0 : (EXTK == kExtWalls ? 1 : 2), MRT)))                  \
+        hipLaunchKernelGGL((k_pool_step<EXTK, MRT>), dim3(kPoolGrid), dim3(kPoolThreads), 0, p->stream,      \
+                           p->d_slots, p->d_hdr, p->d_table, p->tab_s0, p->tab_inv_ds, p->d_errs);
+        LBM_POOL_LAUNCH(kExtNone, false)
+        LBM_POOL_LAUNCH(kExtWalls, false)
+        LBM_POOL_LAUNCH(kExtTable, false)
+        LBM_POOL_LAUNCH(kExtNone, true)
+        LBM_POOL_LAUNCH(kExtWalls, true)
+        LBM_POOL_LAUNCH(kExtTable, true)
+#undef LBM_POOL_LAUNCH
         hipLaunchKernelGGL(k_pool_advance, dim3(adv_blocks), dim3(256), 0, p->stream, p->d_slots,
                            p->d_hdr, p->d_errs);
     }
@@ -449,10 +455,6 @@ lbm_status lbm_pool_submit(lbm_pool* p, const lbm_params* params, const double* 
         set_error("pool requests must be D3Q19, FP32 storage, edges <= %d", kPoolMaxEdge);
         return LBM_EINVAL;
     }
-    if (params->eos != LBM_EOS_VDW) {
-        set_error("pool requests use the van der Waals EOS");
-        return LBM_EINVAL;
-    }
     st = validate_fields(*params, rho0, u0, T0);
     if (st != LBM_OK) return st;
     int slot = -1;
@@ -461,17 +463,25 @@ lbm_status lbm_pool_submit(lbm_pool* p, const lbm_params* params, const double* 
     if (slot < 0) { set_error("no free slot"); return LBM_EBUSY; }
     const size_t half = state_bytes(*params);
     const size_t half_al = (half + kAlign - 1) / kAlign * kAlign;
+    // a tabulated EOS travels with the request: its own copy beside the two buffers
+    const bool table = params->eos == LBM_EOS_TABLE;
+    const size_t np = table ? (size_t)params->eos_nrho * params->eos_nT : 0;
+    const size_t nc = table ? 2 * (size_t)params->eos_nT : 0;
+    const size_t table_al = (sizeof(double) * (np + nc) + kAlign - 1) / kAlign * kAlign;
+    const size_t bytes = 2 * half_al + table_al;
     size_t off = 0;
     if (lbm_status sd = use_device(p->device); sd != LBM_OK) return sd;
-    if (!arena_alloc(p, 2 * half_al, off)) {
-        set_error("request needs %zu bytes; %zu of %zu in use", 2 * half_al, p->in_use, p->budget);
+    if (!arena_alloc(p, bytes, off)) {
+        set_error("request needs %zu bytes; %zu of %zu in use", bytes, p->in_use, p->budget);
         return LBM_EBUSY;
     }
     PoolSlot& ps = p->slots[slot];
     ps.used = true;
     ps.offset = off;
-    ps.bytes = 2 * half_al;
+    ps.bytes = bytes;
     ps.params = *params;
+    ps.params.eos_p = nullptr;     // the caller's table pointers are not kept
+    ps.params.eos_coex = nullptr;
     ps.nsteps = nsteps;
     ps.ticket = p->next_ticket++;
     SlotDesc& d = p->table[slot];
@@ -482,14 +492,24 @@ lbm_status lbm_pool_submit(lbm_pool* p, const lbm_params* params, const double* 
     d.phys = make_phys(*params);
     d.parity = 0;
     d.active = 1;
-    d.kind = ((params->walls || params->gravity[0] != 0.0 || params->gravity[1] != 0.0 ||
-               params->gravity[2] != 0.0) ? 1 : 0) +
-             (params->collision == LBM_COLLISION_MRT ? 2 : 0);
+    const bool ext = params->walls || params->gravity[0] != 0.0 || params->gravity[1] != 0.0 ||
+                     params->gravity[2] != 0.0;
+    d.kind = kind_of(table ? 2 : (ext ? 1 : 0), params->collision == LBM_COLLISION_MRT);
+    d.eos_p = nullptr;
+    d.eos_coex = nullptr;
+    if (table) {
+        d.eos_p = (const double*)(p->arena + off + 2 * half_al);
+        d.eos_coex = d.eos_p + np;
+    }
     d.remaining = nsteps;
     const long long n = (long long)params->nx * params->ny * params->nz;
     // on the side stream: a replay in flight does not touch this free arena block or this
     // slot's error word (the slot is not active on the device)
     hipError_t e = hipMemsetAsync(p->arena + off, 0, 2 * half_al, p->side);
+    if (e == hipSuccess && table)
+        e = hipMemcpyAsync((void*)d.eos_p, params->eos_p, sizeof(double) * np, hipMemcpyHostToDevice, p->side);
+    if (e == hipSuccess && table)
+        e = hipMemcpyAsync((void*)d.eos_coex, params->eos_coex, sizeof(double) * nc, hipMemcpyHostToDevice, p->side);
     if (e == hipSuccess) e = hipMemsetAsync(p->d_errs + slot, 0, sizeof(int), p->side);
     if (e == hipSuccess) e = hipMemcpyAsync(p->d_staging, rho0, sizeof(double) * n, hipMemcpyHostToDevice, p->side);
     if (e == hipSuccess) e = hipMemcpyAsync(p->d_staging + n, u0, sizeof(double) * 3 * n, hipMemcpyHostToDevice, p->side);
@@ -504,7 +524,7 @@ lbm_status lbm_pool_submit(lbm_pool* p, const lbm_params* params, const double* 
     // initial state in place: wait for this upload (not for the replay in flight)
     if (e == hipSuccess) e = hipStreamSynchronize(p->side);
     if (e != hipSuccess) {
-        arena_free(p, off, 2 * half_al);
+        arena_free(p, off, bytes);
         ps = PoolSlot();
         return hip_fail(e, "request upload");
     }
@@ -562,7 +582,7 @@ lbm_status lbm_pool_collect(lbm_pool* p, long long ticket, double* rho, double* 
     int* d_err = p->d_errs + s;
     // on the side stream: the slot has finished, so a replay in flight does not advance it
     hipError_t e = launch_moments(19, 4, d.buf[d.parity], scr, ps.params.nx, ps.params.ny, ps.params.nz,
-                                  d.geom.pitch, d.geom.plane, d.phys, nullptr, d_err, nullptr,
+                                  d.geom.pitch, d.geom.plane, d.phys, d.eos_p, d_err, nullptr,
                                   u_star ? d_us : nullptr, nullptr, nullptr, p->side);
     if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, scr, sizeof(double) * n, hipMemcpyDeviceToHost, p->side);
     if (e == hipSuccess && u_star) e = hipMemcpyAsync(u_star, d_us, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, p->side);
@@ -628,7 +648,7 @@ lbm_status lbm_pool_destroy(lbm_pool* p)
     (void)hipSetDevice(p->device);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     if (p->side) (void)hipStreamSynchronize(p->side);
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < (1 << kPoolKinds); ++k) {
         if (p->exec[k]) (void)hipGraphExecDestroy(p->exec[k]);
         if (p->graph[k]) (void)hipGraphDestroy(p->graph[k]);
     }

@@ -99,11 +99,67 @@ def test_leaving_the_table_is_unstable():
         assert e.value.status == lbm.LBM_EUNSTABLE
 
 
-def test_pool_refuses_table():
-    table = vdw_table()
-    f = I.request_fields(dict(id=0, edge=32, Tr=0.8, kind="droplet", steps=10, seed=I.SEED + 1,
-                              noise=0.01))
-    with lbm.Pool(1 << 30, max_slots=2, steps_per_run=5) as pool:
-        with pytest.raises(lbm.LbmError) as e:
-            pool.submit(dict(f["params"], eos_table=table), f["rho0"], f["u0"], f["T0"], 10)
-        assert e.value.status == lbm.LBM_EINVAL
+def _single(case, steps):
+    with lbm.Sim(19, case["params"], case["rho0"], case["u0"], case["T0"], storage_bytes=4) as s:
+        s.step(steps)
+        return s.moments()
+
+
+def test_pool_runs_table_requests_beside_the_others():
+    """The serving pool takes tabulated-EOS requests (BGK at tau = 1 and 0.8, MRT, walls and
+    gravity) in their own batched launches beside a van der Waals request in the same replays:
+    each result equals its single simulation's bit for bit.  The request keeps its own copy of
+    the table: the caller's arrays are overwritten after submission."""
+    def own():
+        t = vdw_table()
+        return dict(t, p=t["p"].copy(), coex=t["coex"].copy())
+
+    mrt = dict(collision=lbm.LBM_COLLISION_MRT, s_e=1.19, s_eps=1.4, s_q=1.2, s_m=1.98)
+    cases = [
+        I.droplet_3d(shape=(16, 16, 16), radius=4.0),
+        with_table(I.droplet_3d(shape=(16, 20, 24), radius=5.0, velocity=(0.03, 0.0, 0.0)), own()),
+        with_table(I.droplet_3d(shape=(18, 16, 20), radius=5.0, params=I.physics(tau=0.8)), own()),
+        with_table(I.pool_boiling_3d(shape=(20, 16, 24), gravity=1e-4), own()),
+    ]
+    cases[2]["params"] = dict(cases[2]["params"], **mrt)
+    steps = 10
+    singles = [_single(c, steps) for c in cases]
+    with lbm.Pool(1 << 29, max_slots=8, steps_per_run=5) as pool:
+        tickets = []
+        for c in cases:
+            tickets.append(pool.submit(c["params"], c["rho0"], c["u0"], c["T0"], steps))
+            tab = c["params"].get("eos_table")
+            if tab is not None:
+                tab["p"][...] = np.nan
+                tab["coex"][...] = np.nan
+        print("pool: 1 vdW + 3 table requests, %d steps" % steps, flush=True)
+        pool.run()
+        pool.run()
+        for i, (t, ref) in enumerate(zip(tickets, singles)):
+            res, st = pool.collect(t)
+            assert st == lbm.LBM_OK, i
+            for k in res:
+                assert np.array_equal(res[k], ref[k]), (i, k)
+
+
+def test_pool_reports_a_table_request_leaving_the_grid():
+    """The diverging jet in vapour at rho~ = 0.32 with a table starting at 0.3 (the single
+    simulation's case above) leaves the grid in the pool too: collect returns LBM_EUNSTABLE for
+    it, and a van der Waals request in the same replays finishes normally."""
+    table = vdw_table(rho_range=(0.3, 2.6))
+    rho = np.full((16, 16, 16), 0.32)
+    u = np.zeros((3, 16, 16, 16))
+    u[0, :, :, :8] = 0.2
+    u[0, :, :, 8:] = -0.2
+    ok = I.droplet_3d(shape=(16, 16, 16), radius=4.0)
+    with lbm.Pool(1 << 28, max_slots=4, steps_per_run=10) as pool:
+        bad = pool.submit(dict(I.physics(), eos_table=table), rho, u, np.full((16, 16, 16), 0.8), 50)
+        good = pool.submit(ok["params"], ok["rho0"], ok["u0"], ok["T0"], 50)
+        print("pool: table request leaving the grid beside a vdW request", flush=True)
+        for _ in range(5):
+            pool.run()
+        _, st = pool.collect(bad)
+        assert st == lbm.LBM_EUNSTABLE
+        res, st = pool.collect(good)
+        assert st == lbm.LBM_OK
+    assert np.array_equal(res["rho"], _single(ok, 50)["rho"])
