@@ -163,3 +163,27 @@ def test_pool_reports_a_table_request_leaving_the_grid():
         res, st = pool.collect(good)
         assert st == lbm.LBM_OK
     assert np.array_equal(res["rho"], _single(ok, 50)["rho"])
+
+def test_pool_budget_counts_the_table_copy():
+    """A table request's footprint is its two population buffers plus its copy of the table
+    (rounded up to the arena's 256-byte alignment): a budget one alignment unit short of that
+    declines it (LBM_EBUSY, nothing allocated) and still admits the same box with the van der
+    Waals EOS."""
+    table = vdw_table()
+    nT, nrho = table["p"].shape
+    table_bytes = -(-8 * (nrho * nT + 2 * nT) // 256) * 256
+    plain = I.droplet_3d(shape=(16, 16, 16), radius=4.0)
+    tab = with_table(plain, table)
+    with lbm.Pool(1 << 28, max_slots=4, steps_per_run=5) as pool:
+        a = pool.submit(plain["params"], plain["rho0"], plain["u0"], plain["T0"], 5)
+        state = pool.stats()["bytes_in_use"]
+        b = pool.submit(tab["params"], tab["rho0"], tab["u0"], tab["T0"], 5)
+        assert pool.stats()["bytes_in_use"] == 2 * state + table_bytes
+        pool.run()
+        for t in (a, b):
+            assert pool.collect(t)[1] == lbm.LBM_OK
+        assert pool.stats()["bytes_in_use"] == 0
+    with lbm.Pool(state + table_bytes - 256, max_slots=4, steps_per_run=5) as pool:
+        assert pool.submit(tab["params"], tab["rho0"], tab["u0"], tab["T0"], 5) is None
+        assert pool.stats()["bytes_in_use"] == 0
+        assert pool.submit(plain["params"], plain["rho0"], plain["u0"], plain["T0"], 5) is not None
