@@ -198,8 +198,9 @@ lbm_status lbm_reduce(lbm_sim* sim, double out[5]);
  * steps: its collision sums, in FP64, the post-collision populations it stores (section 2,
  * eq:edm; the same quantities as lbm_reduce, out[0..4] as there, equal to them up to the order
  * of the FP64 sums), so the state is not read a second time.  The fields are bitwise those of
- * lbm_step.  The launch variants that have no such fused form (lbm_set_launch variants other
- * than the defaults) run the step and then the separate reduction.  The first call, and any
+ * lbm_step.  The fused form exists for the lbm_set_launch variants 0, 5 and 7 of FP32 D3Q19,
+ * 0 of FP64 D3Q19, 0 and 2 of FP32 D2Q9 and 0 of FP64 D2Q9 (every variant lbm_init starts
+ * with); the others run the step and then the separate reduction.  The first call, and any
  * call after lbm_set_launch raised the workgroup count, allocates a device array of 5 doubles
  * per workgroup that the simulation keeps until lbm_free.  Synchronises; returns
  * LBM_EUNSTABLE like lbm_step (out is then not meaningful) and LBM_EINVAL for nsteps < 1 or
@@ -238,9 +239,11 @@ lbm_status lbm_launch_info(const lbm_sim* sim, int info[4]);
 lbm_status lbm_launch_plan(const lbm_params* params, int cus, int info[4]);
 
 /* Select the launch variant of the fused step kernel (0 .. n-1: tile shape, threads per
- * workgroup, prefetch or LDS stash; D3Q19 has seven with FP32 populations and four with FP64,
- * D2Q9 three: 32x8, 32x16 and 64x8 tiles) and the z-chunk length (0 = automatic).  The default
- * is variant 0.  Results do not depend on the choice (the per-node arithmetic is the same);
+ * workgroup, prefetch or LDS stash; D3Q19 has eight with FP32 populations and four with FP64,
+ * D2Q9 three: 32x8, 32x16 and 64x8 tiles) and the z-chunk length (0 = automatic).  lbm_init
+ * starts with variant 0, except for FP32 D3Q19 states of 4 GB and more whose x extent tiles
+ * at 64 with no more idle columns than at 32: those start with variant 7 (64x8 tiles, global
+ * addressing).  Results do not depend on the choice (the per-node arithmetic is the same);
  * only speed does.  LBM_EINVAL for an unknown variant or a negative chunk. */
 lbm_status lbm_set_launch(lbm_sim* sim, int variant, int chunk);
 

@@ -397,6 +397,17 @@ StepGeom plan_geometry(const lbm_params& p, int variant, int chunk_request, int 
     return g;
 }
 
+// Variant lbm_init starts with: 7 (64 x 8 tiles, global addressing) for FP32 D3Q19 states
+// beyond one buffer resource's 4 GB where 64-wide tiles leave no more x columns idle than
+// 32-wide ones, else 0.
+int default_variant(const lbm_params& p)
+{
+    if (p.lattice != 19 || p.storage_bytes != 4) return 0;
+    if (state_bytes(p) < (1ull << 32)) return 0;
+    const long long w64 = (p.nx + 63LL) / 64 * 64, w32 = (p.nx + 31LL) / 32 * 32;
+    return w64 <= w32 ? 7 : 0;
+}
+
 void choose_geometry(lbm_sim* s, int chunk_request)
 {
     int tx, ty;
@@ -531,6 +542,7 @@ lbm_status lbm_init(const lbm_params* params, const double* rho0, const double* 
         if (e != hipSuccess) { delete s; return hip_fail(e, "hipStreamCreate"); }
         s->own_stream = true;
     }
+    s->variant = default_variant(s->p);
     choose_geometry(s, 0);
     const size_t bytes = state_bytes(s->p);
     hipError_t e = hipMalloc(&s->buf[0], bytes);
@@ -629,7 +641,7 @@ lbm_status lbm_launch_plan(const lbm_params* p, int cus, int info[4])
         return LBM_EINVAL;
     }
     int tx, ty;
-    const StepGeom g = plan_geometry(*p, 0, 0, cus, tx, ty);
+    const StepGeom g = plan_geometry(*p, default_variant(*p), 0, cus, tx, ty);
     info[0] = tx;
     info[1] = ty;
     info[2] = g.chunk;

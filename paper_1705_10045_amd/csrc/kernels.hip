@@ -240,13 +240,15 @@ inline unsigned blocks_for(long long n, int threads)
 // change the per-node arithmetic, so every variant gives bitwise-identical results.
 // `per_cu` is the number of workgroups of the variant resident per compute unit (set by its
 // registers and LDS); the automatic z chunk aims at about 256 * per_cu workgroups.
-// FP32 variant 5 is the default launch with plain global addressing, which states of 4 GB
-// and more use automatically (512^3 and up).
+// FP32 variant 5 is the default launch with plain global addressing, which variant 0 falls
+// back to for states of 4 GB and more; variant 7 is the same on 64 x 8 tiles (816 moment slots,
+// the 48 beyond the 768 threads on threads without collision work), which lbm_init picks for
+// such states where 64-wide tiles leave no more x columns idle than 32-wide ones.
 struct TileShape { int tx, ty, threads; bool pipe, stash; int per_cu; };
 static const TileShape kVariants19f[] = {
     {32, 16, 768, true, true, 1}, {32, 16, 768, false, true, 1}, {32, 16, 768, true, false, 1},
     {32, 16, 768, false, false, 1}, {32, 8, 512, false, false, 2}, {32, 16, 768, true, true, 1},
-    {32, 8, 256, false, false, 2}};
+    {32, 8, 256, false, false, 2}, {64, 8, 768, false, true, 1}};
 constexpr int kNumVariants19f = sizeof(kVariants19f) / sizeof(kVariants19f[0]);
 // FP64 D3Q19: twice the registers and LDS per node
 static const TileShape kVariants19d[] = {
@@ -294,6 +296,7 @@ hipError_t launch_step(int Q, int storage_bytes, int variant, const void* src, v
         case 4: return launch_step_t<19, float, float, 32, 8, 512, false>(src, dst, g, ph, aux, st);
         case 5: return launch_step_t<19, float, float, 32, 16, 768, true, true, true>(src, dst, g, ph, aux, st);
         case 6: return launch_step_t<19, float, float, 32, 8, 256, false>(src, dst, g, ph, aux, st);
+        case 7: return launch_step_t<19, float, float, 64, 8, 768, false, true, true>(src, dst, g, ph, aux, st);
         default: return hipErrorInvalidValue;
         }
     }

@@ -18,6 +18,8 @@ hipError_t launch_step_totals(int Q, int storage_bytes, int variant, const void*
     if (Q == 19 && storage_bytes == 4) {
         if (variant == 0) e = launch_step_t<19, float, float, 32, 16, 512, true, true, false, true>(src, dst, g, ph, aux, st);
         else if (variant == 5) e = launch_step_t<19, float, float, 32, 16, 512, true, true, true, true>(src, dst, g, ph, aux, st);
+        // 64 x 8 tiles: on 512 threads (two moment slots for some) the sums fit the registers
+        else if (variant == 7) e = launch_step_t<19, float, float, 64, 8, 512, false, true, true, true>(src, dst, g, ph, aux, st);
         else return hipErrorNotSupported;
     } else if (Q == 19 && storage_bytes == 8) {
         if (variant == 0) e = launch_step_t<19, double, double, 32, 8, 512, false, true, false, true>(src, dst, g, ph, aux, st);

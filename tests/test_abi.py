@@ -171,19 +171,22 @@ def _rounds_cost(nz, cols, target=256):
 
 
 @pytest.mark.parametrize("shape,expect", [
-    ((512, 512, 512), (32, 16, 512, 512)),
+    ((512, 512, 512), (64, 8, 512, 512)),
     ((128, 128, 128), (32, 16, 16, 256)),
     ((256, 256, 256), (32, 16, 128, 256)),
     ((288, 288, 288), (32, 16, 96, 486)),
-    ((320, 320, 320), (32, 16, 64, 1000)),
-    ((300, 300, 300), (32, 16, 75, 760)),
+    ((320, 320, 320), (64, 8, 64, 1000)),
+    ((300, 300, 300), (64, 8, 75, 760)),
+    ((1024, 320, 96), (32, 16, 256, 240)),
 ])
 def test_launch_plan_of_d3q19_boxes(shape, expect):
-    """The host-only launch plan (no device): 32 x 16 tiles, and the z chunk that minimises the
-    rounds of 256 resident workgroups times the chunk plus its 4 halo planes."""
+    """The host-only launch plan (no device): 32 x 16 tiles, or 64 x 8 for FP32 states of 4 GB
+    and more (288^3 is 3.6 GB) unless 64-wide tiles leave more x columns idle (nx = 96), and
+    the z chunk that minimises the rounds of 256 resident workgroups times the chunk plus its 4
+    halo planes."""
     plan = lbm.lbm_launch_plan(19, shape, I.physics(), 4)
     assert (plan["tile_x"], plan["tile_y"], plan["chunk"], plan["workgroups"]) == expect
-    cols = -(-shape[2] // 32) * -(-shape[1] // 16)
+    cols = -(-shape[2] // plan["tile_x"]) * -(-shape[1] // plan["tile_y"])
     assert plan["chunk"] == _rounds_cost(shape[0], cols)
 
 

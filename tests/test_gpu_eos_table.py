@@ -66,7 +66,7 @@ def test_table_launch_variants_are_bitwise_identical(tau):
     with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"],
                  storage_bytes=4) as s:
         ck = s.checkpoint()
-        for v in range(7):
+        for v in range(8):
             s.set_launch(v, 0)
             s.restore(ck)
             s.step(12)

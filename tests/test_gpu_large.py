@@ -31,15 +31,16 @@ def _moments_after(case, steps, variant=None, storage=4):
 @pytest.mark.parametrize("shape", [NEAR_4GB, BEYOND_4GB])
 def test_large_state_variants_bitwise(tau, shape):
     """Just under 4 GB the default launches (variants 0 and 1) address the state through one
-    buffer resource per buffer, with scalar plane offsets up to 4.2e9 bytes; variant 5 keeps
-    global addressing.  Beyond 4 GB all use global addressing.  Same per-node arithmetic, so the
-    fields agree bit for bit."""
+    buffer resource per buffer, with scalar plane offsets up to 4.2e9 bytes; variants 5 and 7
+    (32 x 16 and 64 x 8 tiles) keep global addressing.  Beyond 4 GB all use global addressing,
+    and lbm_init starts with variant 7 there.  Same per-node arithmetic, so the fields agree bit
+    for bit."""
     case = I.pool_boiling_3d(shape=shape, params=I.physics(tau=tau))
     n = case["rho0"].size
     assert (2 * 19 * 4 * n < (1 << 32)) == (shape == NEAR_4GB)
-    print("large state: pool boiling %s tau %g, variants 0, 1, 5" % (shape, tau), flush=True)
+    print("large state: pool boiling %s tau %g, variants 0, 1, 5, 7" % (shape, tau), flush=True)
     ref = _moments_after(case, 4, 5)
-    for v in (0, 1):
+    for v in (0, 1, 7):
         m = _moments_after(case, 4, v)
         for k in m:
             assert np.array_equal(m[k], ref[k]), (v, k)

@@ -68,10 +68,11 @@ def test_fused_totals_with_mrt_and_the_table(storage):
     _check_totals(ta, tb)
 
 
-@pytest.mark.parametrize("variant", [5, 3])
+@pytest.mark.parametrize("variant", [5, 7, 3])
 def test_fused_totals_global_addressing_and_fallback(variant):
-    """Variant 5 (global addressing, the form of states of 4 GB and more) has the fused form;
-    variant 3 has none and runs the step and then the separate reduction."""
+    """Variants 5 and 7 (global addressing on 32 x 16 and 64 x 8 tiles, the forms of states of
+    4 GB and more) have the fused form; variant 3 has none and runs the step and then the
+    separate reduction."""
     case = CASES["droplet"]()
     ta, tb = _twins(case, 4, 12, variant=variant)
     _check_totals(ta, tb)
