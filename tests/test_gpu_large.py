@@ -121,14 +121,17 @@ def test_pool_boiling_512_against_oracle():
 @pytest.mark.parametrize("n,chunks", [(288, 3), (300, 4)])
 def test_sizes_between_powers_of_two_against_oracle(n, chunks):
     """Cubes between the powers of two in their automatic launch: 288^3 takes 3 z chunks of 96
-    (486 workgroups in two rounds), 300^3 has ragged tiles in x and y, rows padded from 300 to a
-    pitch of 320 and 4 chunks of 75, with global addressing (its padded state exceeds 4 GB).
-    Every field against the oracle after 2 steps."""
+    (486 workgroups in two rounds) on 32 x 16 tiles, 300^3 has ragged tiles in x and y, rows
+    padded from 300 to a pitch of 320 and 4 chunks of 75, with global addressing (its padded
+    state exceeds 4 GB) on 64 x 8 tiles (5 x 38 of them, as many columns as 10 x 19 tiles of
+    32 x 16).  Every field against the oracle after 2 steps."""
     case = I.spinodal_3d(n=n, Tr=0.75, rho_mean=1.0, sigma=0.02)
     print("spinodal %d^3 vs oracle, 2 steps" % n, flush=True)
     with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"]) as s:
         info = s.launch_info()
-        assert (info["chunk"], info["workgroups"]) == (-(-n // chunks), -(-n // 32) * -(-n // 16) * chunks)
+        tx, ty = (32, 16) if n == 288 else (64, 8)
+        assert (info["tile_x"], info["tile_y"]) == (tx, ty)
+        assert (info["chunk"], info["workgroups"]) == (-(-n // chunks), -(-n // tx) * -(-n // ty) * chunks)
         s.step(2)
         g = s.moments()
     o, _ = run_oracle(case, 2)
@@ -141,8 +144,9 @@ def test_sizes_between_powers_of_two_against_oracle(n, chunks):
 def test_two_round_placement_against_oracle():
     """A 512 x 512 x 8 droplet: 512 tiles of 32 x 16 in one z chunk, two rounds of 256, each
     round a band of 16 tile rows shared by the 8 XCDs in runs of 2 rows (the placement of the
-    512^3 launch).  Every field against the oracle after 5 steps, and the same fields, bit for
-    bit, with z chunks of 4 planes (1,024 workgroups in four rounds)."""
+    512^3 launch on those tiles).  Every field against the oracle after 5 steps, and the same
+    fields, bit for bit, with z chunks of 4 planes (1,024 workgroups in four rounds) and on the
+    64 x 8 tiles of variant 7 (the 512^3 default: 512 tiles, bands of 32 tile rows)."""
     case = I.droplet_3d(shape=(8, 512, 512), radius=60.0)
     print("two-round placement: droplet 512x512x8, 5 steps", flush=True)
     with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"]) as s:
@@ -154,8 +158,15 @@ def test_two_round_placement_against_oracle():
         assert s.launch_info()["workgroups"] == 1024
         s.step(5)
         g2 = s.moments()
+    with lbm.Sim(case["Q"], case["params"], case["rho0"], case["u0"], case["T0"]) as s:
+        s.set_launch(7, 0)
+        info = s.launch_info()
+        assert (info["tile_x"], info["tile_y"], info["workgroups"]) == (64, 8, 512)
+        s.step(5)
+        g3 = s.moments()
     for k in g:
         assert np.array_equal(g[k], g2[k]), k
+        assert np.array_equal(g[k], g3[k]), k
     o, _ = run_oracle(case, 5)
     errs = rel_errors(g, o)
     describe("droplet 512x512x8 4B, 5 steps", errs)
